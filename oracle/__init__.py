@@ -1,0 +1,205 @@
+"""Plain FP64 CPU oracle of the successive-convolution fast summation.
+
+TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code with the GPU
+library (``paper_2007_03041_amd``); the arithmetic lives in ``sc_oracle.c`` (plain loops, FP64,
+``-O2 -ffp-contract=off``), and this module only marshals numpy arrays into it.
+
+Paper: Christlieb, Guthrey, Sands, Thavappiragasm (2020), "Parallel Algorithms for Successive
+Convolution".  Section references are given on each function of ``sc_oracle.c``.
+
+Array convention: numpy arrays in C order with shape ``(n[ndim-1], ..., n[0])`` -- axis 0 of the
+grid (x) is the last, contiguous numpy axis.  Periodic axes store ``n`` points with
+``dx = (hi-lo)/n``; Dirichlet axes store both ends with ``dx = (hi-lo)/(n-1)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sc_oracle.c")
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OP_L, OP_R, OP_0 = 0, 1, 2
+BC_PERIODIC, BC_DIRICHLET = 0, 1
+_OPS = {"L": OP_L, "R": OP_R, "0": OP_0, 0: OP_L, 1: OP_R, 2: OP_0}
+_BCS = {"periodic": BC_PERIODIC, "dirichlet": BC_DIRICHLET, 0: BC_PERIODIC, 1: BC_DIRICHLET}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C, OpenMP over independent lines)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH,
+           _SRC, "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    return LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", c_int32), ("n", c_int64 * 3), ("lo", c_double * 3),
+                ("hi", c_double * 3), ("bc", c_int32 * 3)]
+
+
+class _Pde(ctypes.Structure):
+    _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double),
+                ("dt", c_double), ("order", c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(LIB_PATH)
+        dp = POINTER(c_double)
+        lib.sco_weights.argtypes = [c_double, c_int, POINTER(c_int), dp]
+        lib.sco_line_quad.argtypes = [c_int, c_int, c_double, c_double, c_int64, dp, dp, dp]
+        lib.sco_line_sweep.argtypes = [c_int, c_double, c_double, c_int64, dp, dp, dp, dp, dp]
+        lib.sco_line_invL.argtypes = [c_int, c_int, c_int, c_double, c_double, c_int64, dp,
+                                      c_double, c_double, dp]
+        gp = POINTER(_Grid)
+        lib.sco_local_quad.argtypes = [gp, c_int, c_int, c_double, dp, dp, dp]
+        lib.sco_sweep_LR.argtypes = [gp, c_int, c_double, dp, dp, dp, dp, dp]
+        lib.sco_apply_invL.argtypes = [gp, c_int, c_int, c_int, c_double, dp, dp, dp]
+        lib.sco_apply_D_partial_sum.argtypes = [gp, c_int, c_int, c_int, c_double, c_int,
+                                                c_double, dp, dp, dp]
+        lib.sco_time_step.argtypes = [gp, POINTER(_Pde), c_int, dp]
+        lib.sco_num_threads.argtypes = []
+        for f in ("sco_weights", "sco_line_quad", "sco_line_sweep", "sco_line_invL",
+                  "sco_local_quad", "sco_sweep_LR", "sco_apply_invL",
+                  "sco_apply_D_partial_sum", "sco_time_step", "sco_num_threads"):
+            getattr(lib, f).restype = c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def make_grid(n, lo=None, hi=None, bc=None) -> _Grid:
+    """n: tuple (n0[, n1[, n2]]) with n0 = x (contiguous)."""
+    n = tuple(int(v) for v in n)
+    nd = len(n)
+    lo = tuple(lo) if lo is not None else (0.0,) * nd
+    hi = tuple(hi) if hi is not None else (1.0,) * nd
+    bc = tuple(_BCS[b] for b in bc) if bc is not None else (BC_PERIODIC,) * nd
+    g = _Grid()
+    g.ndim = nd
+    for e in range(3):
+        g.n[e] = n[e] if e < nd else 1
+        g.lo[e] = lo[e] if e < nd else 0.0
+        g.hi[e] = hi[e] if e < nd else 1.0
+        g.bc[e] = bc[e] if e < nd else BC_PERIODIC
+    return g
+
+
+def num_threads() -> int:
+    return int(_load().sco_num_threads())
+
+
+def weights(nu: float, eta) -> np.ndarray:
+    """w_j = nu * int_0^1 e^{-nu eta} l_j(eta) d eta on the integer nodes ``eta``."""
+    eta = list(int(e) for e in eta)
+    arr = (c_int * len(eta))(*eta)
+    w = np.zeros(len(eta))
+    _check(_load().sco_weights(float(nu), len(eta), arr, _p(w)), "weights")
+    return w
+
+
+def line_quad(bc, order, alpha, dx, v):
+    v = _f64(v)
+    JL, JR = np.zeros_like(v), np.zeros_like(v)
+    _check(_load().sco_line_quad(_BCS[bc], order, alpha, dx, v.size, _p(v), _p(JL), _p(JR)),
+           "line_quad")
+    return JL, JR
+
+
+def line_sweep(bc, alpha, dx, JL, JR):
+    JL, JR = _f64(JL), _f64(JR)
+    IL, IR, ends = np.zeros_like(JL), np.zeros_like(JL), np.zeros(2)
+    _check(_load().sco_line_sweep(_BCS[bc], alpha, dx, JL.size, _p(JL), _p(JR), _p(IL), _p(IR),
+                                  _p(ends)), "line_sweep")
+    return IL, IR, ends
+
+
+def line_invL(bc, op, order, alpha, dx, v, ga=0.0, gb=0.0):
+    v = _f64(v)
+    out = np.zeros_like(v)
+    _check(_load().sco_line_invL(_BCS[bc], _OPS[op], order, alpha, dx, v.size, _p(v), ga, gb,
+                                 _p(out)), "line_invL")
+    return out
+
+
+def _gvals(g, lines):
+    if g is None:
+        return None
+    g = _f64(g).reshape(-1)
+    if g.size != 2 * lines:
+        raise ValueError("Dirichlet values need 2 per line")
+    return g
+
+
+def local_quad(grid: _Grid, dim, order, alpha, v):
+    v = _f64(v)
+    JL, JR = np.zeros_like(v), np.zeros_like(v)
+    _check(_load().sco_local_quad(ctypes.byref(grid), dim, order, alpha, _p(v), _p(JL), _p(JR)),
+           "local_quad")
+    return JL, JR
+
+
+def sweep_LR(grid: _Grid, dim, alpha, JL, JR):
+    JL, JR = _f64(JL), _f64(JR)
+    IL, IR = np.zeros_like(JL), np.zeros_like(JL)
+    lines = JL.size // grid.n[dim]
+    ends = np.zeros((lines, 2))
+    _check(_load().sco_sweep_LR(ctypes.byref(grid), dim, alpha, _p(JL), _p(JR), _p(IL), _p(IR),
+                                _p(ends)), "sweep_LR")
+    return IL, IR, ends
+
+
+def apply_invL(grid: _Grid, dim, op, order, alpha, v, g=None):
+    v = _f64(v)
+    out = np.zeros_like(v)
+    gv = _gvals(g, v.size // grid.n[dim])
+    _check(_load().sco_apply_invL(ctypes.byref(grid), dim, _OPS[op], order, alpha,
+                                  _p(gv) if gv is not None else None, _p(v), _p(out)),
+           "apply_invL")
+    return out
+
+
+def apply_D_partial_sum(grid: _Grid, dim, op, order, alpha, k, scale, v, g=None):
+    v = _f64(v)
+    out = np.zeros_like(v)
+    gv = _gvals(g, v.size // grid.n[dim])
+    _check(_load().sco_apply_D_partial_sum(ctypes.byref(grid), dim, _OPS[op], order, alpha, k,
+                                           scale, _p(gv) if gv is not None else None, _p(v),
+                                           _p(out)), "apply_D_partial_sum")
+    return out
+
+
+def time_step(grid: _Grid, c, nu_diff, beta, dt, order, nsteps, u):
+    u = _f64(u).copy()
+    p = _Pde()
+    for e in range(3):
+        p.c[e] = c[e] if e < len(c) else 0.0
+    p.nu_diff, p.beta, p.dt, p.order = nu_diff, beta, dt, order
+    _check(_load().sco_time_step(ctypes.byref(grid), ctypes.byref(p), nsteps, _p(u)),
+           "time_step")
+    return u

@@ -1,0 +1,160 @@
+"""Pins of the oracle's time step (CPU only).
+
+A periodic linear step u^{n+1} = u^n - sum_d beta D_{R/L,d}[u^n] - sum_d beta^2 D_{0,d}[u^n]
+(Sec. 2.1 alpha choices, Sec. 2.2 first-order representations, Sec. 2.5 explicit coupling) is
+circulant, so each Fourier mode is multiplied by a scalar symbol per step.  The symbols are built
+from the discrete Fourier symbols of the line operators (weights pinned separately), never from the
+sweeps, and pin the oracle's multi-dimensional step to rounding.  The continuum exact solutions of
+the paper's Examples 1 and 2 then pin first-order convergence, and the printed L-infinity errors of
+Sec. 5.1 are matched in magnitude.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _sym(op, nu, order, theta):
+    ms_R = list(range(-3, 3)) if order == 6 else list(range(-2, 2))
+    ms_L = list(range(-2, 4)) if order == 6 else list(range(-1, 3))
+    wR = oracle.weights(nu, [-m for m in ms_R])
+    wL = oracle.weights(nu, ms_L)
+    d = math.exp(-nu)
+    sR = sum(w * np.exp(1j * theta * m) for m, w in zip(ms_R, wR)) / (1 - d * np.exp(-1j * theta))
+    sL = sum(w * np.exp(1j * theta * m) for m, w in zip(ms_L, wL)) / (1 - d * np.exp(1j * theta))
+    return {"R": sR, "L": sL, "0": 0.5 * (sR + sL)}[op]
+
+
+def _step_symbol(kvec, dxs, c, nu_diff, beta, dt, order):
+    S = 1.0 + 0j
+    for d, (k, dx) in enumerate(zip(kvec, dxs)):
+        th = k * dx
+        if c[d] != 0:
+            a = beta / (abs(c[d]) * dt)
+            op = "R" if c[d] > 0 else "L"
+            S -= abs(c[d]) * dt * a * (1 - _sym(op, a * dx, order, th))
+        if nu_diff > 0:
+            a = beta / math.sqrt(nu_diff * dt)
+            S -= nu_diff * dt * a * a * (1 - _sym("0", a * dx, order, th))
+    return S
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_two_dimensional_step_matches_mode_symbols(order):
+    n = (48, 40)
+    L = (2 * np.pi, 2 * np.pi)
+    dxs = [L[d] / n[d] for d in range(2)]
+    x = np.arange(n[0]) * dxs[0]
+    y = np.arange(n[1]) * dxs[1]
+    X, Y = np.meshgrid(x, y)  # shape (n1, n0)
+    modes = [((1, 2), 0.7, 0.3), ((-3, 1), -0.4, 1.1), ((5, -4), 0.25, 2.0)]
+    c, nu_diff, beta, dt, steps = (1.0, -0.5), 0.3, 1.0, 0.05, 3
+    u0 = sum(a * np.cos(k[0] * X + k[1] * Y + ph) for k, a, ph in modes)
+    g = oracle.make_grid(n, (0, 0), L)
+    got = oracle.time_step(g, c, nu_diff, beta, dt, order, steps, u0)
+    ref = sum(np.real(a * np.exp(1j * ph) * _step_symbol(k, dxs, c, nu_diff, beta, dt, order) ** steps
+                      * np.exp(1j * (k[0] * X + k[1] * Y))) for k, a, ph in modes)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_three_dimensional_step_matches_mode_symbols():
+    n = (12, 10, 9)
+    L = (1.0, 2.0, 1.5)
+    dxs = [L[d] / n[d] for d in range(3)]
+    Z, Y, X = np.meshgrid(np.arange(n[2]) * dxs[2], np.arange(n[1]) * dxs[1],
+                          np.arange(n[0]) * dxs[0], indexing="ij")
+    k = (2 * np.pi * 2 / L[0], 2 * np.pi * 1 / L[1], 2 * np.pi * -1 / L[2])
+    u0 = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+    c, nu_diff, beta, dt = (0.3, 0.0, -1.0), 0.05, 1.0, 0.02
+    g = oracle.make_grid(n, (0, 0, 0), L)
+    got = oracle.time_step(g, c, nu_diff, beta, dt, 4, 2, u0)
+    S = _step_symbol(k, dxs, c, nu_diff, beta, dt, 4)
+    ref = np.real(S ** 2 * np.exp(1j * (k[0] * X + k[1] * Y + k[2] * Z)))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_dirichlet_heat_step_keeps_boundary_and_matches_continuum_symbol():
+    """3-D heat with zero Dirichlet data: sin(pi x) sin(pi y) sin(pi z) is an eigenfunction of each
+    continuum L_0^{-1} with value alpha^2/(alpha^2+pi^2), so one additive step multiplies it by
+    1 - 3 pi^2/(alpha^2 + pi^2); the discrete step converges to that at sixth order (shifted
+    one-sided stencils included) and keeps the boundary at zero."""
+    dt = 1.0 / 16
+    a = 1.0 / math.sqrt(dt)
+    pred = 1 - 3 * math.pi ** 2 / (a * a + math.pi ** 2)
+    errs = []
+    for m in (17, 33, 65):
+        n = (m, m, m)
+        g = oracle.make_grid(n, (0, 0, 0), (1, 1, 1), ("dirichlet",) * 3)
+        Z, Y, X = np.meshgrid(*[np.linspace(0, 1, m)] * 3, indexing="ij")
+        u0 = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+        u1 = oracle.time_step(g, (0, 0, 0), 1.0, 1.0, dt, 6, 1, u0)
+        for face in (u1[0], u1[-1], u1[:, 0], u1[:, -1], u1[:, :, 0], u1[:, :, -1]):
+            assert np.abs(face).max() < 1e-15
+        errs.append(np.abs(u1 - pred * u0).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 5.5, (errs, rates)
+
+
+def _paper_errors():
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_convergence_errors.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, T, err = [t.strip() for t in line.split("|")]
+        rows[name] = (float(T), float(err))
+    return rows
+
+
+def _example_error(example, N, order=6):
+    """L-inf error of Example 1 or 2 at N^2 from the per-mode step symbols (beta = 1, dt ~ dx)."""
+    dx = 2 * np.pi / N
+    if example == "advection":
+        T, _ = _paper_errors()["advection"]
+        steps = int(round(T / dx))
+        dt = T / steps
+        c, nu = (1.0, 1.0), 0.0
+        modes = [((1, 0), -0.25), ((0, 1), -0.25), ((1, 1), 0.125), ((1, -1), 0.125)]
+        exact = lambda k: np.exp(-1j * (k[0] + k[1]) * T)
+    else:
+        T, _ = _paper_errors()["diffusion"]
+        steps = int(round(T / dx))
+        dt = T / steps
+        c, nu = (0.0, 0.0), 1.0
+        modes = [((1, 0), -0.5j), ((0, 1), -0.5j)]  # sin = Im e^{i x}: coefficient of e^{ikx} + c.c.
+        exact = lambda k: np.exp(-(k[0] ** 2 + k[1] ** 2) * T)
+    xs = np.arange(0, N, max(1, N // 512)) * dx  # sampled grid points
+    X, Y = np.meshgrid(xs, xs)
+    err = np.zeros_like(X)
+    for k, a in modes:
+        S = _step_symbol(k, (dx, dx), c, nu, 1.0, dt, order)
+        diff = (S ** steps - exact(k)) * a * np.exp(1j * (k[0] * X + k[1] * Y))
+        err = err + 2 * np.real(diff) if example == "diffusion" else err + np.real(diff)
+    return np.abs(err).max()
+
+
+@pytest.mark.parametrize("example", ["advection", "diffusion"])
+def test_printed_linf_errors_magnitude_and_first_order(example):
+    """Parity with the printed digits is unpinned (grid/step conventions unstated); the symbol-exact
+    error of this repository's reading is within a factor 2 of the printed value and first order."""
+    _, printed = _paper_errors()[example]
+    e = _example_error(example, 5277)
+    assert printed / 2 < e < printed * 2, (e, printed)
+    e1, e2 = _example_error(example, 1000), _example_error(example, 2000)
+    assert abs(math.log2(e1 / e2) - 1.0) < 0.1
+
+
+def test_symbol_error_matches_oracle_run_on_small_grid():
+    """Example 2 at 32^2 for a few steps: the oracle run equals the symbol prediction."""
+    N = 32
+    dx = 2 * np.pi / N
+    x = np.arange(N) * dx
+    X, Y = np.meshgrid(x, x)
+    g = oracle.make_grid((N, N), (0, 0), (2 * np.pi, 2 * np.pi))
+    u = oracle.time_step(g, (0.0, 0.0), 1.0, 1.0, dx, 6, 4, np.sin(X) + np.sin(Y))
+    S = _step_symbol((1, 0), (dx, dx), (0, 0), 1.0, 1.0, dx, 6)
+    ref = np.real(S ** 4) * (np.sin(X) + np.sin(Y))
+    np.testing.assert_allclose(u, ref, rtol=0, atol=1e-14)
