@@ -1,0 +1,142 @@
+/*
+ * sc.h -- C ABI of the MI355X (gfx950) successive-convolution library.
+ *
+ * The library applies, line by line along one axis of a dense 1-3 dimensional array, the
+ * exponential-kernel convolution operators of Christlieb, Guthrey, Sands & Thavappiragasm (2020),
+ * "Parallel Algorithms for Successive Convolution":
+ *   L_L^{-1}[v](x) = alpha int_x^b e^{-alpha(s-x)} v ds + B e^{-alpha(b-x)}          (Sec. 2.1)
+ *   L_R^{-1}[v](x) = alpha int_a^x e^{-alpha(x-s)} v ds + A e^{-alpha(x-a)}          (Sec. 2.1)
+ *   L_0^{-1}[v](x) = alpha/2 int_a^b e^{-alpha|x-s|} v ds + A e^{-alpha(x-a)} + B e^{-alpha(b-x)}
+ * computed in O(N) per line by local quadrature (Sec. 2.4, eqs. (JR), (JL); sixth-order rule of
+ * Sec. 2.4 / App. C, or its centred fourth-order substencil), two recursive sweeps
+ * I_R(x_i) = e^{-alpha dx} I_R(x_{i-1}) + J_R(x_i), I_L(x_i) = e^{-alpha dx} I_L(x_{i+1}) + J_L(x_i)
+ * (Sec. 2.4), and the boundary constants A, B (Sec. 2.3 periodic; Dirichlet values enforced at the
+ * two ends, App. A).  D = I - L^{-1} and its partial sums (Sec. 2.2) stand in for derivatives.
+ *
+ * Memory and ownership
+ *   - All array pointers are DEVICE pointers owned by the caller (hipMalloc or torch tensors),
+ *     dense, C order, axis 0 (x) contiguous: element (i0, i1, i2) at i0 + n0*(i1 + n1*i2).
+ *   - Pointers to arrays of the data type must be aligned to the element size; the library never
+ *     allocates device memory and keeps no state between calls except read-only tables.
+ *   - Every call is asynchronous on `stream` (0 = the null stream); SC_OK means "validated and
+ *     enqueued".  Device-side faults surface at the caller's next synchronisation.
+ *   - `out` must not overlap `v`.  Workspace buffers (`ws`) are caller-owned device memory of at
+ *     least sc_workspace_bytes() bytes, 256-byte aligned; their contents on entry are ignored.
+ *
+ * Grid conventions (SC_BC_PERIODIC): n stored points x_i = lo + i*dx, dx = (hi-lo)/n, the point
+ * x_n = x_0 is not stored.  SC_BC_DIRICHLET: n stored points including both ends, dx = (hi-lo)/(n-1).
+ * "Lines" of axis d are numbered row-major over the remaining axes (highest axis slowest); Dirichlet
+ * values are given as 2 doubles per line (value at lo, value at hi), NULL meaning zero.
+ *
+ * Errors: every function returns an sc_status; on failure nothing is enqueued and sc_last_error()
+ * returns a message (thread-local, valid until the next call on the same thread).  No C++
+ * exception crosses this interface.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *sc_stream_t; /* hipStream_t */
+
+typedef enum {
+    SC_OK = 0,
+    SC_ERR_ARG = -1,         /* invalid argument (null pointer, alpha <= 0, bad dim/op/k, overlap) */
+    SC_ERR_SHAPE = -2,       /* line too short for the stencil, or sizes out of range */
+    SC_ERR_UNSUPPORTED = -3, /* valid request the library does not implement */
+    SC_ERR_WORKSPACE = -4,   /* workspace missing or smaller than sc_workspace_bytes() */
+    SC_ERR_DEVICE = -5       /* a HIP call or kernel launch failed */
+} sc_status;
+
+typedef enum {
+    SC_F64 = 0,      /* FP64 data and arithmetic */
+    SC_F32_MIXED = 1 /* FP32 data, quadrature and in-segment sweeps with compensated carries;
+                        FP64 boundary constants (A,B) and cross-segment / cross-chunk carries */
+} sc_dtype;
+
+typedef enum { SC_OP_L = 0, SC_OP_R = 1, SC_OP_0 = 2 } sc_op; /* L_L^{-1}, L_R^{-1}, L_0^{-1} */
+typedef enum { SC_BC_PERIODIC = 0, SC_BC_DIRICHLET = 1 } sc_bc;
+
+typedef struct {
+    int32_t ndim;     /* 1..3 */
+    int64_t n[3];     /* stored points per axis; n[0] = x (contiguous); unused axes = 1 */
+    double lo[3];     /* domain [lo, hi] per axis */
+    double hi[3];
+    int32_t bc[3];    /* sc_bc per axis */
+    int32_t dtype;    /* sc_dtype: element type of every array argument */
+} sc_grid;
+
+/* Local integrals along axis `dim` (Sec. 2.4, eqs. (JR), (JL)); order 4 or 6.
+ * JR[i] integrates cell [x_{i-1}, x_i], JL[i] cell [x_i, x_{i+1}] (periodic: wrapped cells at the
+ * ends; Dirichlet: JR = 0 at the first and JL = 0 at the last point, one-sided 6/4-point stencils
+ * within order/2 points of an end).  v, JL, JR: arrays of the grid's shape and dtype. */
+sc_status sc_local_quad(const sc_grid *grid, int dim, int order, double alpha, const void *v,
+                        void *JL, void *JR, sc_stream_t stream);
+
+/* Raw recursive sweeps along `dim` (Sec. 2.4): IR[0] = 0, IR[i] = d IR[i-1] + JR[i];
+ * IL[last] = JL[last], IL[i] = d IL[i+1] + JL[i], d = e^{-alpha dx}.  line_ends (FP64, 2 per line):
+ * [I_L(a), I_R(b)] with I_R(b) = d IR[n-1] + JR[0] for periodic axes.  No boundary constants. */
+sc_status sc_sweep_LR(const sc_grid *grid, int dim, double alpha, const void *JL, const void *JR,
+                      void *IL, void *IR, double *line_ends, sc_stream_t stream);
+
+/* out = L_op^{-1}[v] along `dim` with the boundary constants of Sec. 2.3 (periodic) or the
+ * Dirichlet values (2 per line, FP64, device; NULL = 0).  ws: see sc_workspace_bytes(). */
+sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+                        const double *dirichlet_g, const void *v, void *out, void *ws,
+                        size_t ws_bytes, sc_stream_t stream);
+
+/* out = scale * sum_{p=1..k} D^p[v], D = I - L_op^{-1} (Sec. 2.2, successive relation), k in 1..8.
+ * scale = +alpha, -alpha, -alpha^2 gives the left-biased, right-biased and second derivative
+ * representations.  Dirichlet axes support k = 1 only (SC_ERR_UNSUPPORTED otherwise). */
+sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+                                 int k, double scale, const double *dirichlet_g, const void *v,
+                                 void *out, void *ws, size_t ws_bytes, sc_stream_t stream);
+
+/* u_t + c . grad u = nu_diff lap u, advanced `nsteps` forward-Euler steps in place:
+ *   u <- u - sum_d |c_d| dt alpha_d D_{R or L, d}[u] - sum_d nu_diff dt alpha_nu^2 D_{0,d}[u]
+ * with alpha_d = beta/(|c_d| dt) (D_R if c_d > 0, D_L if c_d < 0) and alpha_nu = beta/sqrt(nu dt)
+ * (Sec. 2.1 alpha choices; Sec. 2.2 first-order representations; Sec. 2.5 explicit coupling).
+ * Dirichlet axes hold u = 0 at both ends.  nn_policy applies the nearest-neighbour time-step bound
+ * of Sec. 3.1 with tolerance nn_eps over blocks of length block_len (0 = the whole axis):
+ * 0 = ignore, 1 = reduce dt to the bound, 2 = fail with SC_ERR_ARG if dt exceeds it. */
+typedef struct {
+    double c[3];
+    double nu_diff;
+    double beta;
+    double dt;
+    int32_t order;    /* 4 or 6 */
+    int32_t nn_policy;
+    double nn_eps;    /* 0 -> 1e-16 */
+    double block_len; /* 0 -> axis length */
+} sc_linear_pde;
+
+sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps, void *u,
+                       void *ws, size_t ws_bytes, sc_stream_t stream);
+
+/* Workspace bytes needed by one call: which = 0 sc_apply_invL, 1 sc_apply_D_partial_sum (for k),
+ * 2 sc_time_step.  Returns 0 on invalid arguments. */
+size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k);
+
+/* The time step actually used by sc_time_step for this pde (after the nearest-neighbour policy),
+ * or a negative value on invalid arguments. */
+double sc_effective_dt(const sc_grid *grid, const sc_linear_pde *pde);
+
+const char *sc_last_error(void);
+
+/* Optional per-kernel timing with HIP events recorded on the caller's stream around every launch
+ * the library makes (for benchmarks).  sc_timing_read returns the number of kernel names written;
+ * ms[i] is the summed elapsed time and counts[i] the launches of names[i] since the last reset.
+ * Reading synchronises the events. */
+sc_status sc_timing_enable(int on);
+int sc_timing_read(char names[][64], double *ms, int *counts, int max_entries);
+void sc_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,294 @@
+"""MI355X (gfx950) successive-convolution library -- thin Python binding of ``libsc.so``.
+
+This module only marshals arguments: torch tensors supply device memory and the current HIP
+stream; every step of the computation runs in the library's HIP kernels (see ``include/sc.h``).
+If the library is not built, every entry point raises -- there is no CPU fallback.
+
+Array convention: a grid with ``n = (n0, n1, n2)`` is a contiguous tensor of shape
+``(n2, n1, n0)`` (axis 0 = x is the last, contiguous tensor dimension); 1-D and 2-D grids drop the
+leading dimensions.  ``dim`` counts grid axes (0 = x).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsc.so")
+
+SC_OK, SC_ERR_ARG, SC_ERR_SHAPE, SC_ERR_UNSUPPORTED, SC_ERR_WORKSPACE, SC_ERR_DEVICE = 0, -1, -2, -3, -4, -5
+SC_F64, SC_F32_MIXED = 0, 1
+OPS = {"L": 0, "R": 1, "0": 2}
+BCS = {"periodic": 0, "dirichlet": 1}
+_STATUS = {0: "SC_OK", -1: "SC_ERR_ARG", -2: "SC_ERR_SHAPE", -3: "SC_ERR_UNSUPPORTED",
+           -4: "SC_ERR_WORKSPACE", -5: "SC_ERR_DEVICE"}
+
+# exported symbols of include/sc.h
+SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum",
+           "sc_time_step", "sc_workspace_bytes", "sc_effective_dt", "sc_last_error",
+           "sc_timing_enable", "sc_timing_read", "sc_timing_reset")
+
+
+class ScError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sc_grid(ctypes.Structure):
+    _fields_ = [("ndim", c_int32), ("n", c_int64 * 3), ("lo", c_double * 3), ("hi", c_double * 3),
+                ("bc", c_int32 * 3), ("dtype", c_int32)]
+
+
+class sc_linear_pde(ctypes.Structure):
+    _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double), ("dt", c_double),
+                ("order", c_int32), ("nn_policy", c_int32), ("nn_eps", c_double),
+                ("block_len", c_double)]
+
+
+@dataclass
+class Grid:
+    """Uniform grid: ``n[0]`` is the contiguous x axis."""
+    n: Sequence[int]
+    lo: Sequence[float] = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    hi: Sequence[float] = field(default_factory=lambda: (1.0, 1.0, 1.0))
+    bc: Sequence[str] = field(default_factory=lambda: ("periodic",) * 3)
+    dtype: int = SC_F64
+
+    def c(self) -> sc_grid:
+        g = sc_grid()
+        nd = len(self.n)
+        g.ndim = nd
+        for e in range(3):
+            g.n[e] = int(self.n[e]) if e < nd else 1
+            g.lo[e] = float(self.lo[e]) if e < nd else 0.0
+            g.hi[e] = float(self.hi[e]) if e < nd else 1.0
+            g.bc[e] = BCS[self.bc[e]] if e < nd else 0
+        g.dtype = self.dtype
+        return g
+
+    @property
+    def shape(self):
+        return tuple(int(x) for x in reversed(list(self.n)))
+
+    def dx(self, dim: int) -> float:
+        cells = self.n[dim] if self.bc[dim] == "periodic" else self.n[dim] - 1
+        return (self.hi[dim] - self.lo[dim]) / cells
+
+
+_lib = None
+
+
+def load():
+    """Load ``libsc.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_03041_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    gp = POINTER(sc_grid)
+    lib.sc_local_quad.argtypes = [gp, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.sc_sweep_LR.argtypes = [gp, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p]
+    lib.sc_apply_invL.argtypes = [gp, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_size_t, c_void_p]
+    lib.sc_apply_D_partial_sum.argtypes = [gp, c_int, c_int, c_int, c_double, c_int, c_double, c_void_p,
+                                           c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.sc_time_step.argtypes = [gp, POINTER(sc_linear_pde), c_int, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.sc_workspace_bytes.argtypes = [gp, c_int, c_int, c_int]
+    lib.sc_workspace_bytes.restype = c_size_t
+    lib.sc_effective_dt.argtypes = [gp, POINTER(sc_linear_pde)]
+    lib.sc_effective_dt.restype = c_double
+    lib.sc_last_error.argtypes = []
+    lib.sc_last_error.restype = c_char_p
+    lib.sc_timing_enable.argtypes = [c_int]
+    lib.sc_timing_read.argtypes = [POINTER(c_char * 64), POINTER(c_double), POINTER(c_int), c_int]
+    lib.sc_timing_read.restype = c_int
+    lib.sc_timing_reset.argtypes = []
+    lib.sc_timing_reset.restype = None
+    for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum", "sc_time_step",
+              "sc_timing_enable"):
+        getattr(lib, f).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SC_OK:
+        raise ScError(status, load().sc_last_error().decode())
+
+
+def _stream() -> int:
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _tensor_ok(t, grid: Grid, name: str):
+    import torch
+
+    want = torch.float64 if grid.dtype == SC_F64 else torch.float32
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    n = 1
+    for x in grid.n:
+        n *= int(x)
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, grid has {n}")
+
+
+def _workspace(nbytes: int, device):
+    import torch
+
+    if nbytes == 0:
+        return None, 0
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+def _gptr(g, grid: Grid, dim: int):
+    if g is None:
+        return None
+    import torch
+
+    lines = 1
+    for e, x in enumerate(grid.n):
+        if e != dim:
+            lines *= int(x)
+    if not (g.is_cuda and g.dtype == torch.float64 and g.is_contiguous() and g.numel() == 2 * lines):
+        raise ValueError("Dirichlet values: contiguous float64 device tensor with 2 values per line")
+    return g.data_ptr()
+
+
+def workspace_bytes(grid: Grid, dim: int, which: int, k: int = 1) -> int:
+    gc = grid.c()
+    return int(load().sc_workspace_bytes(ctypes.byref(gc), dim, which, k))
+
+
+def local_quad(v, grid: Grid, dim: int, order: int, alpha: float):
+    """(J_L, J_R) along ``dim``."""
+    import torch
+
+    lib = load()
+    _tensor_ok(v, grid, "v")
+    JL, JR = torch.empty_like(v), torch.empty_like(v)
+    gc = grid.c()
+    _check(lib.sc_local_quad(ctypes.byref(gc), dim, order, alpha, v.data_ptr(), JL.data_ptr(), JR.data_ptr(),
+                             _stream()))
+    return JL, JR
+
+
+def sweep_LR(JL, JR, grid: Grid, dim: int, alpha: float):
+    """(I_L, I_R, line_ends[lines, 2]) raw sweeps along ``dim``."""
+    import torch
+
+    lib = load()
+    _tensor_ok(JL, grid, "JL")
+    _tensor_ok(JR, grid, "JR")
+    IL, IR = torch.empty_like(JL), torch.empty_like(JL)
+    lines = JL.numel() // int(grid.n[dim])
+    ends = torch.empty((lines, 2), dtype=torch.float64, device=JL.device)
+    gc = grid.c()
+    _check(lib.sc_sweep_LR(ctypes.byref(gc), dim, alpha, JL.data_ptr(), JR.data_ptr(), IL.data_ptr(),
+                           IR.data_ptr(), ends.data_ptr(), _stream()))
+    return IL, IR, ends
+
+
+def apply_invL(v, grid: Grid, dim: int, op: str, order: int, alpha: float, g=None, out=None):
+    """out = L_op^{-1}[v] along ``dim``."""
+    import torch
+
+    lib = load()
+    _tensor_ok(v, grid, "v")
+    out = torch.empty_like(v) if out is None else out
+    _tensor_ok(out, grid, "out")
+    gc = grid.c()
+    ws, wsp = _workspace(int(lib.sc_workspace_bytes(ctypes.byref(gc), dim, 0, 0)), v.device)
+    nbytes = 0 if ws is None else ws.numel() - 256
+    _check(lib.sc_apply_invL(ctypes.byref(gc), dim, OPS[op], order, alpha, _gptr(g, grid, dim), v.data_ptr(),
+                             out.data_ptr(), wsp, nbytes, _stream()))
+    return out
+
+
+def apply_D_partial_sum(v, grid: Grid, dim: int, op: str, order: int, alpha: float, k: int = 1,
+                        scale: float = 1.0, g=None, out=None):
+    """out = scale * sum_{p=1..k} D^p[v] along ``dim``."""
+    import torch
+
+    lib = load()
+    _tensor_ok(v, grid, "v")
+    out = torch.empty_like(v) if out is None else out
+    _tensor_ok(out, grid, "out")
+    gc = grid.c()
+    ws, wsp = _workspace(int(lib.sc_workspace_bytes(ctypes.byref(gc), dim, 1, k)), v.device)
+    nbytes = 0 if ws is None else ws.numel() - 256
+    _check(lib.sc_apply_D_partial_sum(ctypes.byref(gc), dim, OPS[op], order, alpha, k, scale,
+                                      _gptr(g, grid, dim), v.data_ptr(), out.data_ptr(), wsp, nbytes,
+                                      _stream()))
+    return out
+
+
+def make_pde(c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6, nn_policy=0, nn_eps=0.0,
+             block_len=0.0) -> sc_linear_pde:
+    p = sc_linear_pde()
+    for e in range(3):
+        p.c[e] = float(c[e]) if e < len(c) else 0.0
+    p.nu_diff, p.beta, p.dt, p.order = float(nu_diff), float(beta), float(dt), int(order)
+    p.nn_policy, p.nn_eps, p.block_len = int(nn_policy), float(nn_eps), float(block_len)
+    return p
+
+
+class TimeStepper:
+    """Holds the workspace of repeated ``sc_time_step`` calls on one grid (allocated once)."""
+
+    def __init__(self, grid: Grid, pde: sc_linear_pde, device="cuda"):
+        self.grid, self.pde = grid, pde
+        self._gc = grid.c()
+        nbytes = int(load().sc_workspace_bytes(ctypes.byref(self._gc), 0, 2, 1))
+        self._ws, self._wsp = _workspace(nbytes, device)
+        self._nbytes = nbytes
+
+    def step(self, u, nsteps: int = 1):
+        _tensor_ok(u, self.grid, "u")
+        _check(load().sc_time_step(ctypes.byref(self._gc), ctypes.byref(self.pde), nsteps, u.data_ptr(),
+                                   self._wsp, self._nbytes, _stream()))
+        return u
+
+
+def time_step(u, grid: Grid, nsteps: int, c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6,
+              nn_policy=0, nn_eps=0.0, block_len=0.0):
+    """Advance u (in place) by ``nsteps`` first-order steps of u_t + c.grad u = nu_diff lap u."""
+    pde = make_pde(c, nu_diff, beta, dt, order, nn_policy, nn_eps, block_len)
+    return TimeStepper(grid, pde, u.device).step(u, nsteps)
+
+
+def effective_dt(grid: Grid, pde: sc_linear_pde) -> float:
+    gc = grid.c()
+    return float(load().sc_effective_dt(ctypes.byref(gc), ctypes.byref(pde)))
+
+
+def timing_enable(on: bool = True):
+    _check(load().sc_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    load().sc_timing_reset()
+
+
+def timing_read(max_entries: int = 32):
+    """{kernel name: (total ms, launches)} since the last reset (synchronises the events)."""
+    lib = load()
+    names = (c_char * 64 * max_entries)()
+    ms = (c_double * max_entries)()
+    cnt = (c_int * max_entries)()
+    m = lib.sc_timing_read(ctypes.cast(names, POINTER(c_char * 64)), ms, cnt, max_entries)
+    return {bytes(names[i]).split(b"\0", 1)[0].decode(): (ms[i], cnt[i]) for i in range(m)}

@@ -1,0 +1,520 @@
+// sc_api.cpp -- the C ABI of include/sc.h: validation, coefficient set-up, pass planning and the
+// time-step driver.  All arithmetic on array data happens in the HIP kernels (sc_kernels.hip);
+// this file only prepares per-axis constants (quadrature weights, decay powers, mu) in FP64 and
+// enqueues launches on the caller's stream.
+#include "sc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sc_device.h"
+#include "sc_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sc_status fail(sc_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// optional per-kernel timing (events on the caller's stream)
+// ------------------------------------------------------------------------------------------
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_records;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
+size_t g_pool_used = 0;
+
+template <typename F>
+hipError_t timed(const char *fallback_name, hipStream_t st, F &&launch)
+{
+    if (!g_timing) {
+        const char *nm = fallback_name;
+        return launch(&nm);
+    }
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (g_pool_used == g_pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
+        g_pool.emplace_back(a, b);
+    }
+    auto ev = g_pool[g_pool_used++];
+    hipError_t e = hipEventRecord(ev.first, st);
+    if (e != hipSuccess) return e;
+    const char *nm = fallback_name;
+    e = launch(&nm);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev.second, st);
+    if (e != hipSuccess) return e;
+    g_records.push_back({nm ? std::string(nm) : std::string(fallback_name), ev.first, ev.second});
+    return e;
+}
+
+// ------------------------------------------------------------------------------------------
+// grid helpers
+// ------------------------------------------------------------------------------------------
+struct Axis {
+    int64_t n, stride, nlines, ncells, total;
+    double dx, len;
+    int bc;
+};
+
+sc_status check_grid(const sc_grid *g)
+{
+    if (!g) return fail(SC_ERR_ARG, "grid is NULL");
+    if (g->ndim < 1 || g->ndim > 3) return fail(SC_ERR_ARG, "ndim must be 1, 2 or 3");
+    if (g->dtype != SC_F64 && g->dtype != SC_F32_MIXED) return fail(SC_ERR_ARG, "unknown dtype");
+    if (g->dtype != SC_F64) return fail(SC_ERR_UNSUPPORTED, "only SC_F64 is implemented in this build");
+    int64_t total = 1;
+    for (int e = 0; e < g->ndim; ++e) {
+        if (g->n[e] < 1) return fail(SC_ERR_SHAPE, "n must be >= 1 on every axis");
+        if (g->bc[e] != SC_BC_PERIODIC && g->bc[e] != SC_BC_DIRICHLET) return fail(SC_ERR_ARG, "unknown bc");
+        if (!(g->hi[e] > g->lo[e]) || !std::isfinite(g->hi[e] - g->lo[e]))
+            return fail(SC_ERR_ARG, "each axis needs lo < hi");
+        if (total > (int64_t(1) << 40) / g->n[e]) return fail(SC_ERR_SHAPE, "array too large");
+        total *= g->n[e];
+    }
+    return SC_OK;
+}
+
+Axis axis_of(const sc_grid *g, int dim)
+{
+    Axis a;
+    a.n = g->n[dim];
+    a.stride = 1;
+    for (int e = 0; e < dim; ++e) a.stride *= g->n[e];
+    a.total = 1;
+    for (int e = 0; e < g->ndim; ++e) a.total *= g->n[e];
+    a.nlines = a.total / a.n;
+    a.bc = g->bc[dim];
+    a.ncells = a.bc == SC_BC_PERIODIC ? a.n : a.n - 1;
+    a.len = g->hi[dim] - g->lo[dim];
+    a.dx = a.len / (double)a.ncells;
+    return a;
+}
+
+size_t elem_bytes(const sc_grid *g) { return g->dtype == SC_F64 ? 8 : 4; }
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool overlap(const void *a, const void *b, size_t bytes)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+// Per-(axis, operator, alpha) constants for the variant chosen for the pass.
+void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, int variant,
+             int64_t chunk, double scale, int k)
+{
+    std::memset(P, 0, sizeof(*P));
+    const int H = order / 2;
+    const double nu = alpha * ax.dx;
+    int eta[8];
+    // interior: window offset j <-> node x_{i-H+j} <-> eta = H - j (J_R); J_L uses the mirror
+    for (int j = 0; j < order; ++j) eta[j] = H - j;
+    scx::quad_weights(nu, order, eta, P->wR);
+    // Dirichlet one-sided stencils (nodes 0..order-1 at the left end, n-order..n-1 at the right)
+    for (int q = 0; q + 1 < H; ++q) {
+        int i = q + 1;  // J_R at i, nodes j: eta = i - j
+        for (int j = 0; j < order; ++j) eta[j] = i - j;
+        scx::quad_weights(nu, order, eta, P->bRl[q]);
+        // J_R at i = n-H+1+q with nodes n-order+j: eta = (order - H + 1 + q) - j
+        for (int j = 0; j < order; ++j) eta[j] = (order - H + 1 + q) - j;
+        scx::quad_weights(nu, order, eta, P->bRr[q]);
+        // J_L at i = q with nodes j: eta = j - q
+        for (int j = 0; j < order; ++j) eta[j] = j - q;
+        scx::quad_weights(nu, order, eta, P->bLl[q]);
+        // J_L at i = n-H+q with nodes n-order+j: eta = j - order + H - q
+        for (int j = 0; j < order; ++j) eta[j] = j - order + H - q;
+        scx::quad_weights(nu, order, eta, P->bLr[q]);
+    }
+    const int S = scx::variant_S(variant);
+    const int GW = scx::variant_GW(variant);
+    P->d = std::exp(-nu);
+    P->nu = nu;
+    for (int t = 0; t <= scx::MAXS; ++t) P->dpow[t] = std::exp(-nu * t);
+    for (int j = 0; j < 8; ++j) P->dseg[j] = std::exp(-nu * (double)S * (double)(1 << j));
+    P->dpart = std::exp(-nu * (double)S * (double)GW);
+    P->dchunk = std::exp(-nu * (double)chunk);
+    const double x = nu * (double)ax.ncells;  // alpha (b - a)
+    P->mu = std::exp(-x);
+    P->inv1mmu = 1.0 / (-std::expm1(-x));
+    P->scale = scale;
+    P->op = op;
+    P->k = k;
+}
+
+struct OpSpec {
+    int op;
+    double alpha, scale;
+    int k;
+};
+
+size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops)
+{
+    if (nchunks <= 1) return 0;
+    const int64_t ent = (int64_t)nops * nlines * nchunks;
+    return round256(sizeof(double) * (size_t)(3 * ent)) +
+           round256(sizeof(double) * (size_t)(2 * ent + 2 * (int64_t)nops * nlines));
+}
+
+int64_t nchunks_for(const Axis &ax)
+{
+    int variant;
+    const int64_t C = scx::pick_chunk(ax.stride == 1, ax.n, &variant);
+    return (ax.n + C - 1) / C;
+}
+
+// One pass along `dim`: out = acc_term + sum_ops scale * result(op).
+sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v,
+                   const void *acc, int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes,
+                   hipStream_t st)
+{
+    const Axis ax = axis_of(g, dim);
+    int variant;
+    const int64_t C = scx::pick_chunk(ax.stride == 1, ax.n, &variant);
+    scx::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.acc = acc;
+    a.out = out;
+    a.g = dg;
+    a.n = ax.n;
+    a.stride = ax.stride;
+    a.nlines = ax.nlines;
+    a.ncells = ax.ncells;
+    a.nchunks = (ax.n + C - 1) / C;
+    a.bc = ax.bc;
+    a.acc_mode = acc_mode;
+    a.nops = nops;
+    for (int o = 0; o < nops; ++o)
+        fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, variant, C, ops[o].scale, ops[o].k);
+    hipError_t e;
+    if (a.nchunks == 1) {
+        e = timed("line_pass_fused", st, [&](const char **nm) {
+            return scx::launch_line_pass(a, order, variant, scx::LMODE_FUSED, st, nm);
+        });
+        if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        return SC_OK;
+    }
+    const size_t need = chunk_ws_bytes(ax.nlines, a.nchunks, nops);
+    if (!wsp || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small for a chunked pass");
+    const int64_t ent = (int64_t)nops * ax.nlines * a.nchunks;
+    a.agg = (double *)wsp;
+    a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
+    e = timed("line_pass_agg", st, [&](const char **nm) {
+        return scx::launch_line_pass(a, order, variant, scx::LMODE_AGG, st, nm);
+    });
+    if (e == hipSuccess)
+        e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, C, st); });
+    if (e == hipSuccess)
+        e = timed("line_pass_apply", st, [&](const char **nm) {
+            return scx::launch_line_pass(a, order, variant, scx::LMODE_APPLY, st, nm);
+        });
+    if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return SC_OK;
+}
+
+sc_status check_line_args(const sc_grid *g, int dim, int order, double alpha)
+{
+    sc_status s = check_grid(g);
+    if (s != SC_OK) return s;
+    if (dim < 0 || dim >= g->ndim) return fail(SC_ERR_ARG, "dim out of range");
+    if (order != 4 && order != 6) return fail(SC_ERR_UNSUPPORTED, "order must be 4 or 6");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(SC_ERR_ARG, "alpha must be finite and > 0");
+    if (g->n[dim] < order + 1) return fail(SC_ERR_SHAPE, "line shorter than the stencil (n < order + 1)");
+    const double nu = alpha * (axis_of(g, dim).dx);
+    if (!(nu < 700.0)) return fail(SC_ERR_ARG, "alpha * dx too large (> 700)");
+    return SC_OK;
+}
+
+double nn_bound(const sc_grid *g, const sc_linear_pde *p)
+{
+    const double eps = p->nn_eps > 0.0 ? p->nn_eps : 1e-16;
+    const double le = std::log(eps);
+    double b = std::numeric_limits<double>::infinity();
+    for (int d = 0; d < g->ndim; ++d) {
+        const double Lm = p->block_len > 0.0 ? p->block_len : (g->hi[d] - g->lo[d]);
+        if (p->c[d] != 0.0) b = std::min(b, -p->beta * Lm / (std::fabs(p->c[d]) * le));
+        if (p->nu_diff > 0.0) b = std::min(b, (1.0 / p->nu_diff) * (p->beta * Lm / le) * (p->beta * Lm / le));
+    }
+    return b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// ABI
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char *sc_last_error(void) { return g_err.c_str(); }
+
+sc_status sc_local_quad(const sc_grid *grid, int dim, int order, double alpha, const void *v, void *JL,
+                        void *JR, sc_stream_t stream)
+{
+    sc_status s = check_line_args(grid, dim, order, alpha);
+    if (s != SC_OK) return s;
+    if (!v || !JL || !JR) return fail(SC_ERR_ARG, "null array pointer");
+    const Axis ax = axis_of(grid, dim);
+    const size_t bytes = (size_t)ax.total * elem_bytes(grid);
+    if (overlap(v, JL, bytes) || overlap(v, JR, bytes) || overlap(JL, JR, bytes))
+        return fail(SC_ERR_ARG, "v, JL and JR must not overlap");
+    scx::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.n = ax.n;
+    a.stride = ax.stride;
+    a.nlines = ax.nlines;
+    a.ncells = ax.ncells;
+    a.bc = ax.bc;
+    a.nops = 1;
+    fill_op(&a.ops[0], SC_OP_0, order, alpha, ax, 0, 1, 1.0, 0);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = timed("local_quad", st, [&](const char **) { return scx::launch_local_quad(a, order, JL, JR, st); });
+    if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return SC_OK;
+}
+
+sc_status sc_sweep_LR(const sc_grid *grid, int dim, double alpha, const void *JL, const void *JR, void *IL,
+                      void *IR, double *line_ends, sc_stream_t stream)
+{
+    sc_status s = check_line_args(grid, dim, 4, alpha);
+    if (s != SC_OK) return s;
+    if (!JL || !JR || !IL || !IR || !line_ends) return fail(SC_ERR_ARG, "null array pointer");
+    const Axis ax = axis_of(grid, dim);
+    const size_t bytes = (size_t)ax.total * elem_bytes(grid);
+    if (overlap(IL, IR, bytes) || overlap(IL, JL, bytes) || overlap(IL, JR, bytes) || overlap(IR, JL, bytes) ||
+        overlap(IR, JR, bytes))
+        return fail(SC_ERR_ARG, "outputs must not overlap the inputs or each other");
+    scx::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = ax.n;
+    a.stride = ax.stride;
+    a.nlines = ax.nlines;
+    a.ncells = ax.ncells;
+    a.bc = ax.bc;
+    a.nops = 1;
+    a.ops[0].d = std::exp(-alpha * ax.dx);
+    a.ops[0].nu = alpha * ax.dx;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = timed("sweep", st, [&](const char **) { return scx::launch_sweep(a, JL, JR, IL, IR, line_ends, st); });
+    if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return SC_OK;
+}
+
+size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k)
+{
+    if (check_grid(grid) != SC_OK) return 0;
+    if (which == 2) {
+        size_t b = round256((size_t)axis_of(grid, 0).total * elem_bytes(grid));
+        size_t extra = 0;
+        for (int d = 0; d < grid->ndim; ++d) {
+            const Axis ax = axis_of(grid, d);
+            extra = std::max(extra, chunk_ws_bytes(ax.nlines, nchunks_for(ax), 2));
+        }
+        return b + extra + 256;
+    }
+    if (dim < 0 || dim >= grid->ndim) return 0;
+    const Axis ax = axis_of(grid, dim);
+    const int64_t nch = nchunks_for(ax);
+    size_t b = chunk_ws_bytes(ax.nlines, nch, 1);
+    if (which == 1 && nch > 1 && k > 1) b += 2 * round256((size_t)ax.total * elem_bytes(grid));
+    return b + 256;
+}
+
+sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, double alpha, const double *dirichlet_g,
+                        const void *v, void *out, void *ws, size_t ws_bytes, sc_stream_t stream)
+{
+    sc_status s = check_line_args(grid, dim, order, alpha);
+    if (s != SC_OK) return s;
+    if (op < SC_OP_L || op > SC_OP_0) return fail(SC_ERR_ARG, "op must be SC_OP_L, SC_OP_R or SC_OP_0");
+    if (!v || !out) return fail(SC_ERR_ARG, "null array pointer");
+    const Axis ax = axis_of(grid, dim);
+    if (overlap(v, out, (size_t)ax.total * elem_bytes(grid))) return fail(SC_ERR_ARG, "out overlaps v");
+    if (ws && ((uintptr_t)ws & 255)) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
+    OpSpec o{(int)op, alpha, 1.0, 0};
+    return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes,
+                    (hipStream_t)stream);
+}
+
+sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int order, double alpha, int k,
+                                 double scale, const double *dirichlet_g, const void *v, void *out, void *ws,
+                                 size_t ws_bytes, sc_stream_t stream)
+{
+    sc_status s = check_line_args(grid, dim, order, alpha);
+    if (s != SC_OK) return s;
+    if (op < SC_OP_L || op > SC_OP_0) return fail(SC_ERR_ARG, "op must be SC_OP_L, SC_OP_R or SC_OP_0");
+    if (k < 1 || k > 8) return fail(SC_ERR_ARG, "k must be in 1..8");
+    if (!std::isfinite(scale)) return fail(SC_ERR_ARG, "scale must be finite");
+    if (!v || !out) return fail(SC_ERR_ARG, "null array pointer");
+    if (grid->bc[dim] == SC_BC_DIRICHLET && k > 1)
+        return fail(SC_ERR_UNSUPPORTED, "Dirichlet axes support k = 1 only");
+    const Axis ax = axis_of(grid, dim);
+    const size_t bytes = (size_t)ax.total * elem_bytes(grid);
+    if (overlap(v, out, bytes)) return fail(SC_ERR_ARG, "out overlaps v");
+    if (ws && ((uintptr_t)ws & 255)) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (nchunks_for(ax) == 1 || k == 1) {
+        OpSpec o{(int)op, alpha, scale, k};
+        return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes, st);
+    }
+    // chunked lines and k > 1: w_p = D[w_{p-1}] pass by pass, out accumulates scale * w_p
+    const size_t need = sc_workspace_bytes(grid, dim, 1, k);
+    if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small");
+    char *w0 = (char *)ws;
+    char *w1 = w0 + round256(bytes);
+    char *rest = w1 + round256(bytes);
+    const size_t rest_bytes = ws_bytes - 2 * round256(bytes);
+    const void *prev = v;
+    for (int p = 1; p <= k; ++p) {
+        char *dst = (p % 2) ? w0 : w1;
+        OpSpec o{(int)op, alpha, 1.0, 1};
+        s = run_pass(grid, dim, order, &o, 1, prev, nullptr, 0, dst, dirichlet_g, rest, rest_bytes, st);
+        if (s != SC_OK) return s;
+        hipError_t e = timed("axpy", st, [&](const char **) {
+            return scx::launch_axpy(ax.total, scale, dst, out, p == 1 ? 1 : 0, st);
+        });
+        if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        prev = dst;
+    }
+    return SC_OK;
+}
+
+double sc_effective_dt(const sc_grid *grid, const sc_linear_pde *pde)
+{
+    if (check_grid(grid) != SC_OK || !pde || !(pde->dt > 0.0) || !(pde->beta > 0.0)) return -1.0;
+    if (pde->nn_policy == 1) return std::min(pde->dt, nn_bound(grid, pde));
+    return pde->dt;
+}
+
+sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps, void *u, void *ws,
+                       size_t ws_bytes, sc_stream_t stream)
+{
+    sc_status s = check_grid(grid);
+    if (s != SC_OK) return s;
+    if (!pde || !u) return fail(SC_ERR_ARG, "null argument");
+    if (nsteps < 0) return fail(SC_ERR_ARG, "nsteps must be >= 0");
+    if (pde->order != 4 && pde->order != 6) return fail(SC_ERR_UNSUPPORTED, "order must be 4 or 6");
+    if (!(pde->dt > 0.0) || !(pde->beta > 0.0) || !(pde->nu_diff >= 0.0))
+        return fail(SC_ERR_ARG, "dt and beta must be > 0 and nu_diff >= 0");
+    if (pde->nn_policy < 0 || pde->nn_policy > 2) return fail(SC_ERR_ARG, "nn_policy must be 0, 1 or 2");
+    double dt = pde->dt;
+    if (pde->nn_policy != 0) {
+        const double bound = nn_bound(grid, pde);
+        if (dt > bound) {
+            if (pde->nn_policy == 2) return fail(SC_ERR_ARG, "dt exceeds the nearest-neighbour bound");
+            dt = bound;
+        }
+    }
+    for (int d = 0; d < grid->ndim; ++d)
+        if (grid->n[d] < pde->order + 1) return fail(SC_ERR_SHAPE, "line shorter than the stencil");
+    const size_t need = sc_workspace_bytes(grid, 0, 2, 1);
+    if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small (see sc_workspace_bytes)");
+    if ((uintptr_t)ws & 255) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
+    const Axis ax0 = axis_of(grid, 0);
+    const size_t fbytes = (size_t)ax0.total * elem_bytes(grid);
+    if (overlap(u, ws, fbytes)) return fail(SC_ERR_ARG, "workspace overlaps u");
+    hipStream_t st = (hipStream_t)stream;
+    char *wsp = (char *)ws;
+    void *cur = u, *nxt = wsp;
+    char *rest = wsp + round256(fbytes);
+    const size_t rest_bytes = ws_bytes - round256(fbytes);
+    // per-axis operators (Sec. 2.1 alpha choices)
+    OpSpec ops[3][2];
+    int nops[3] = {0, 0, 0};
+    for (int d = 0; d < grid->ndim; ++d) {
+        const double c = pde->c[d];
+        if (c != 0.0) {
+            const double a = pde->beta / (std::fabs(c) * dt);
+            ops[d][nops[d]++] = OpSpec{c > 0.0 ? SC_OP_R : SC_OP_L, a, -std::fabs(c) * dt * a, 1};
+        }
+        if (pde->nu_diff > 0.0) {
+            const double a = pde->beta / std::sqrt(pde->nu_diff * dt);
+            ops[d][nops[d]++] = OpSpec{SC_OP_0, a, -pde->nu_diff * dt * a * a, 1};
+        }
+        for (int o = 0; o < nops[d]; ++o) {
+            const double nu = ops[d][o].alpha * axis_of(grid, d).dx;
+            if (!(nu < 700.0) || !std::isfinite(nu)) return fail(SC_ERR_ARG, "alpha * dx too large (> 700)");
+        }
+    }
+    for (int step = 0; step < nsteps; ++step) {
+        bool first = true;
+        for (int d = 0; d < grid->ndim; ++d) {
+            if (!nops[d]) continue;
+            s = run_pass(grid, d, pde->order, ops[d], nops[d], cur, first ? nullptr : nxt, first ? 1 : 2, nxt, nullptr,
+                         rest, rest_bytes, st);
+            if (s != SC_OK) return s;
+            first = false;
+        }
+        if (!first) std::swap(cur, nxt);
+    }
+    if (cur != u) {
+        hipError_t e = hipMemcpyAsync(u, cur, fbytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("copy failed: ") + hipGetErrorString(e));
+    }
+    return SC_OK;
+}
+
+sc_status sc_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return SC_OK;
+}
+
+void sc_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &r : g_records) (void)hipEventSynchronize(r.stop);
+    g_records.clear();
+    g_pool_used = 0;
+}
+
+int sc_timing_read(char names[][64], double *ms, int *counts, int max_entries)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    std::vector<std::string> nm;
+    std::vector<double> t;
+    std::vector<int> cnt;
+    for (auto &r : g_records) {
+        float el = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&el, r.start, r.stop) != hipSuccess)
+            el = 0.f;
+        size_t i = 0;
+        for (; i < nm.size(); ++i)
+            if (nm[i] == r.name) break;
+        if (i == nm.size()) {
+            nm.push_back(r.name);
+            t.push_back(0.0);
+            cnt.push_back(0);
+        }
+        t[i] += el;
+        cnt[i] += 1;
+    }
+    int m = 0;
+    for (size_t i = 0; i < nm.size() && m < max_entries; ++i, ++m) {
+        std::snprintf(names[m], 64, "%s", nm[i].c_str());
+        ms[m] = t[i];
+        counts[m] = cnt[i];
+    }
+    return m;
+}
+
+}  // extern "C"

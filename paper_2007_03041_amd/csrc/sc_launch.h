@@ -1,0 +1,28 @@
+// sc_launch.h -- host launchers of the kernels in sc_kernels.hip (library internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc_device.h"
+
+namespace scx {
+
+enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2 };
+
+// Kernel variant for a pass: returns the chunk length C (points of one line per workgroup).
+int64_t pick_chunk(bool contig, int64_t n, int *variant);
+int variant_S(int variant);
+int variant_GW(int variant);
+
+hipError_t launch_line_pass(const PassArgs &a, int order, int variant, int mode, hipStream_t st,
+                            const char **name);
+hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st);
+hipError_t launch_local_quad(const PassArgs &a, int order, void *JL, void *JR, hipStream_t st);
+hipError_t launch_sweep(const PassArgs &a, const void *JL, const void *JR, void *IL, void *IR,
+                        double *ends, hipStream_t st);
+hipError_t launch_axpy(int64_t nel, double s, const void *x, void *y, int init, hipStream_t st);
+
+double moment(int q, double nu);
+void quad_weights(double nu, int m, const int *eta, double *w);
+
+}  // namespace scx

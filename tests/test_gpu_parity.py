@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances (FP64 path): L^{-1} and time-step results within 1e-12 * ||ref||_inf; D and its partial
+sums within 1e-12 * ||v||_inf (D = v - L^{-1} v cancels by up to (alpha/k)^2, so the backward-stable
+scale of its error is the operand's, not the result's).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_03041_amd import Grid, ScError
+from paper_2007_03041_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+OPS = ("L", "R", "0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def ogrid(g: Grid):
+    return oracle.make_grid(g.n, g.lo, g.hi, g.bc)
+
+
+def err(got, ref, scale):
+    return float(np.abs(got - ref).max() / max(scale, 1e-300))
+
+
+# ------------------------------------------------------------------------------ config 1 (1-D)
+@pytest.mark.parametrize("op", OPS)
+def test_config1_line_invL_and_partial_sums(gpu_lib, op):
+    sc = gpu_lib
+    N = 1024
+    v = W.noisy_sine_line(N, index=1)
+    g = Grid((N,), (0.0,), (1.0,), ("periodic",))
+    alpha = 1.0 / (1.0 * (1.0 / N))  # beta / (c dt), dt = dx
+    ref = oracle.apply_invL(ogrid(g), 0, op, 6, alpha, v)
+    got = host(sc.apply_invL(dev(v), g, 0, op, 6, alpha))
+    assert err(got, ref, np.abs(ref).max()) < TOL
+    for k in (1, 2, 3):
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, op, 6, alpha, k, 1.0, v)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, op, 6, alpha, k, 1.0))
+        assert err(got, ref, np.abs(v).max()) < TOL, k
+
+
+def test_config1_replicated_lines(gpu_lib):
+    sc = gpu_lib
+    N, lines = 1024, 300
+    v = W.noisy_sine_line(N, index=1, lines=lines)
+    g = Grid((N, lines), (0.0, 0.0), (1.0, 1.0))
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, op, 6, 1024.0, 3, -1024.0 ** 2, v)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, op, 6, 1024.0, 3, -1024.0 ** 2))
+        assert err(got, ref, 1024.0 ** 2 * np.abs(v).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ ragged 1-D lines
+CASES = []
+_r = np.random.default_rng(5)
+for n in (7, 9, 64, 100, 129, 511, 513, 1000, 2049, 4096, 4097, 9000):
+    for bc in ("periodic", "dirichlet"):
+        for order in (4, 6):
+            CASES.append((n, bc, order, float(10 ** _r.uniform(-2, math.log10(20)))))
+
+
+@pytest.mark.parametrize("n,bc,order,nu", CASES)
+def test_ragged_lines_contiguous(gpu_lib, n, bc, order, nu):
+    sc = gpu_lib
+    lines = 3
+    v = W.random_field((lines, n), index=20 + n)
+    g = Grid((n, lines), (0.0, 0.0), (2.0, 1.0), (bc, "periodic"))
+    alpha = nu / g.dx(0)
+    gv = np.random.default_rng(n).standard_normal((lines, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_invL(ogrid(g), 0, op, order, alpha, v, gv)
+        got = host(sc.apply_invL(dev(v), g, 0, op, order, alpha, g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, op, order, alpha, 1, 1.0, v, gv)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, op, order, alpha, 1, 1.0,
+                                          g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(v).max()) < TOL, op
+    if bc == "periodic":
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, "0", order, alpha, 3, 1.0, v)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, "0", order, alpha, 3, 1.0))
+        assert err(got, ref, np.abs(v).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ strided axes
+SHAPES = [
+    ((41, 37, 5), ("periodic", "dirichlet", "periodic")),
+    ((20, 1100, 3), ("periodic", "periodic", "periodic")),   # y lines longer than one tile
+    ((17, 2, 600), ("dirichlet", "periodic", "dirichlet")),  # z lines longer than one tile
+    ((33, 130, 9), ("dirichlet", "dirichlet", "periodic")),
+]
+
+
+@pytest.mark.parametrize("n,bcs", SHAPES)
+def test_all_axes(gpu_lib, n, bcs):
+    sc = gpu_lib
+    shape = tuple(reversed(n))
+    v = W.random_field(shape, index=40 + n[1])
+    g = Grid(n, (0.0, -1.0, 0.5), (1.0, 2.0, 1.5), bcs)
+    rng = np.random.default_rng(sum(n))
+    for dim in range(3):
+        if n[dim] < 7:
+            continue
+        alpha = float(rng.uniform(0.05, 5.0)) / g.dx(dim)
+        lines = v.size // n[dim]
+        gv = rng.standard_normal((lines, 2)) if bcs[dim] == "dirichlet" else None
+        for order in (4, 6):
+            for op in OPS:
+                ref = oracle.apply_invL(ogrid(g), dim, op, order, alpha, v, gv)
+                got = host(sc.apply_invL(dev(v), g, dim, op, order, alpha,
+                                         g=None if gv is None else dev(gv)))
+                assert err(got, ref, np.abs(ref).max()) < TOL, (dim, order, op)
+        if bcs[dim] == "periodic":
+            ref = oracle.apply_D_partial_sum(ogrid(g), dim, "R", 6, alpha, 2, alpha, v)
+            got = host(sc.apply_D_partial_sum(dev(v), g, dim, "R", 6, alpha, 2, alpha))
+            assert err(got, ref, alpha * np.abs(v).max()) < TOL, dim
+
+
+# ------------------------------------------------------------------------------ stages
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_local_quad_and_sweeps(gpu_lib, bc):
+    sc = gpu_lib
+    n = (300, 7, 2)
+    v = W.random_field(tuple(reversed(n)), index=77)
+    g = Grid(n, (0, 0, 0), (1, 1, 1), (bc, bc, "periodic"))
+    for dim, order in ((0, 6), (1, 4)):
+        alpha = 0.7 / g.dx(dim)
+        JLr, JRr = oracle.local_quad(ogrid(g), dim, order, alpha, v)
+        JL, JR = sc.local_quad(dev(v), g, dim, order, alpha)
+        assert err(host(JL), JLr, np.abs(JLr).max()) < TOL
+        assert err(host(JR), JRr, np.abs(JRr).max()) < TOL
+        ILr, IRr, ends_r = oracle.sweep_LR(ogrid(g), dim, alpha, JLr, JRr)
+        IL, IR, ends = sc.sweep_LR(dev(JLr), dev(JRr), g, dim, alpha)
+        assert err(host(IL), ILr, np.abs(ILr).max()) < TOL
+        assert err(host(IR), IRr, np.abs(IRr).max()) < TOL
+        assert err(host(ends), ends_r, np.abs(ends_r).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ time steps
+def test_time_step_2d_advection_diffusion_small(gpu_lib):
+    sc = gpu_lib
+    N = 256
+    u0 = W.fourier_field(N, N)
+    g = Grid((N, N), (0, 0), (2 * np.pi, 2 * np.pi))
+    dt = 2 * np.pi / N
+    ref = oracle.time_step(ogrid(g), (1.0, 1.0), 1.0, 1.0, dt, 4, 3, u0)
+    u = dev(u0)
+    sc.time_step(u, g, 3, c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dt, order=4)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
+
+
+def test_time_step_mixed_signs_nonsquare(gpu_lib):
+    sc = gpu_lib
+    n = (96, 1030)  # y lines chunked
+    u0 = W.random_field((n[1], n[0]), index=90)
+    g = Grid(n, (0, 0), (1.0, 3.0))
+    ref = oracle.time_step(ogrid(g), (-0.7, 0.4), 0.05, 1.0, 0.01, 6, 2, u0)
+    u = dev(u0)
+    sc.time_step(u, g, 2, c=(-0.7, 0.4), nu_diff=0.05, beta=1.0, dt=0.01, order=6)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
+
+
+def test_time_step_3d_dirichlet_heat(gpu_lib):
+    sc = gpu_lib
+    n = 33
+    u0 = W.bump_field(n)
+    g = Grid((n, n, n), (0, 0, 0), (1, 1, 1), ("dirichlet",) * 3)
+    dt = 1.0 / (n - 1)
+    ref = oracle.time_step(ogrid(g), (0, 0, 0), 1.0, 1.0, dt, 6, 2, u0)
+    u = dev(u0)
+    sc.time_step(u, g, 2, nu_diff=1.0, beta=1.0, dt=dt, order=6)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ full sizes
+def test_config2_full_size_one_step_sampled(gpu_lib):
+    """4096^2, order 4, one step in the benchmark's launch configuration; sampled points are
+    recomputed by the oracle from their own row and column."""
+    sc = gpu_lib
+    N = 4096
+    L = 2 * np.pi
+    dx = L / N
+    g = Grid((N, N), (0, 0), (L, L))
+    u = W.fourier_field(N, N, device="cuda")
+    u0 = host(u).copy()
+    sc.time_step(u, g, 1, c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dx, order=4)
+    got = host(u)
+    a_adv, a_dif = 1.0 / dx, 1.0 / math.sqrt(dx)
+    rng = np.random.default_rng(4096)
+    rows = rng.choice(N, 6, replace=False)
+    cols = rng.choice(N, 6, replace=False)
+    for j in rows:
+        row = u0[j]
+        dR = row - oracle.line_invL("periodic", "R", 4, a_adv, dx, row)
+        d0 = row - oracle.line_invL("periodic", "0", 4, a_dif, dx, row)
+        for i in cols:
+            col = u0[:, i]
+            eR = col - oracle.line_invL("periodic", "R", 4, a_adv, dx, col)
+            e0 = col - oracle.line_invL("periodic", "0", 4, a_dif, dx, col)
+            ref = u0[j, i] - dR[i] - d0[i] - eR[j] - e0[j]
+            assert abs(got[j, i] - ref) < TOL * np.abs(u0).max()
+
+
+def test_config2_ten_steps_match_mode_symbols(gpu_lib):
+    """The 8-mode initial data evolves mode by mode: after 10 steps each mode is multiplied by
+    S(k)^10 with S built from the discrete symbols (weights from the oracle)."""
+    sc = gpu_lib
+    N = 4096
+    L = 2 * np.pi
+    dx = L / N
+    g = Grid((N, N), (0, 0), (L, L))
+    u = W.fourier_field(N, N, device="cuda")
+    sc.time_step(u, g, 10, c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dx, order=4)
+    got = host(u)
+
+    def sym(op, nu, th):
+        mR, mL = list(range(-2, 2)), list(range(-1, 3))
+        wR = oracle.weights(nu, [-m for m in mR])
+        wL = oracle.weights(nu, mL)
+        d = math.exp(-nu)
+        sR = sum(w * np.exp(1j * th * m) for m, w in zip(mR, wR)) / (1 - d * np.exp(-1j * th))
+        sL = sum(w * np.exp(1j * th * m) for m, w in zip(mL, wL)) / (1 - d * np.exp(1j * th))
+        return sR if op == "R" else 0.5 * (sR + sL)
+
+    a_adv, a_dif = 1.0 / dx, 1.0 / math.sqrt(dx)
+    ks, amp, phase = W.fourier_modes(index=2)
+    rng = np.random.default_rng(10)
+    js, is_ = rng.choice(N, 64), rng.choice(N, 64)
+    x, y = is_ * dx, js * dx
+    ref = np.zeros(64)
+    for (kx, ky), a, ph in zip(ks, amp, phase):
+        S = 1.0
+        for k in (kx, ky):
+            th = k * dx
+            S -= (1 - sym("R", a_adv * dx, th)) + (1 - sym("0", a_dif * dx, th))
+        ref += np.real(a * np.exp(1j * ph) * S ** 10 * np.exp(1j * (kx * x + ky * y)))
+    assert np.abs(got[js, is_] - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_config3_full_size_one_step_sampled(gpu_lib):
+    """512^3 Dirichlet heat, order 6, one step; sampled points from their x, y and z lines."""
+    sc = gpu_lib
+    n = 512
+    dx = 1.0 / (n - 1)
+    g = Grid((n, n, n), (0, 0, 0), (1, 1, 1), ("dirichlet",) * 3)
+    u = W.bump_field(n, device="cuda")
+    u0 = host(u).copy()
+    sc.time_step(u, g, 1, nu_diff=1.0, beta=1.0, dt=dx, order=6)
+    got = host(u)
+    a = 1.0 / math.sqrt(dx)
+    rng = np.random.default_rng(512)
+    for _ in range(12):
+        k, j, i = rng.integers(0, n, 3)
+        ref = u0[k, j, i]
+        for line, pos in ((u0[k, j, :], i), (u0[k, :, i], j), (u0[:, j, i], k)):
+            ref -= line[pos] - oracle.line_invL("dirichlet", "0", 6, a, dx, line)[pos]
+        assert abs(got[k, j, i] - ref) < TOL * np.abs(u0).max()
+
+
+# ------------------------------------------------------------------------------ errors
+def test_invalid_arguments_raise(gpu_lib):
+    sc = gpu_lib
+    v = dev(np.ones(64))
+    g = Grid((64,))
+    with pytest.raises(ScError):
+        sc.apply_invL(v, g, 0, "0", 5, 10.0)       # bad order
+    with pytest.raises(ScError):
+        sc.apply_invL(v, g, 0, "0", 6, -1.0)       # alpha <= 0
+    with pytest.raises(ScError):
+        sc.apply_invL(v, g, 1, "0", 6, 10.0)       # bad dim
+    with pytest.raises(ScError):
+        sc.apply_D_partial_sum(v, g, 0, "0", 6, 10.0, k=9)
+    with pytest.raises(ScError):
+        sc.apply_invL(dev(np.ones(6)), Grid((6,)), 0, "0", 6, 10.0)  # too short
+    with pytest.raises(ScError):
+        sc.apply_invL(v, g, 0, "0", 6, 10.0, out=v)  # aliasing
+    gd = Grid((64,), bc=("dirichlet",))
+    with pytest.raises(ScError):
+        sc.apply_D_partial_sum(v, gd, 0, "0", 6, 10.0, k=2)  # unsupported
+
+
+def test_nonfinite_input_propagates(gpu_lib):
+    sc = gpu_lib
+    a = np.ones(100)
+    a[50] = np.nan
+    out = host(sc.apply_invL(dev(a), Grid((100,)), 0, "0", 6, 100.0))
+    assert np.isnan(out).any()
+
+
+def test_repeat_runs_bitwise_identical(gpu_lib):
+    """No LDS race: the same launch twice gives identical bits."""
+    sc = gpu_lib
+    n = (4096, 64)
+    v = dev(W.random_field((64, 4096), index=3))
+    g = Grid(n)
+    a = host(sc.apply_D_partial_sum(v, g, 0, "0", 6, 900.0, 3, 1.0)).copy()
+    b = host(sc.apply_D_partial_sum(v, g, 0, "0", 6, 900.0, 3, 1.0))
+    assert np.array_equal(a, b)
+    a = host(sc.apply_invL(v, g, 1, "R", 4, 30.0)).copy()
+    b = host(sc.apply_invL(v, g, 1, "R", 4, 30.0))
+    assert np.array_equal(a, b)
