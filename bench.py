@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the successive-convolution hot path on one MI355X.
+
+Workload: 2-D linear advection-diffusion u_t + u_x + u_y = lap u on [0, 2 pi]^2, 4096 x 4096,
+periodic, FP64, fourth-order local quadrature, dimension-split x then y, dt = dx, beta = 1; initial
+data 8 seeded random Fourier modes (|k| <= 16, amplitudes U(-1, 1)).  One "step" is one time step:
+an x pass applying D_R and D_0 to every x line and a y pass applying them to every y line
+(4 one-dimensional operator applications per DOF).
+
+Prints one JSON line.  ``value`` = DOF x operator applications / s (the per-application update
+rate); ``paper_metric_dof_per_s`` = DOF / (time per step), the paper's DOF/node/s with one GPU as
+the node.  ``roofline`` reports the dominant kernel's algorithmic HBM bytes (16 B per DOF: read the
+operand, write the result) over its mean duration measured with HIP events recorded by the library
+on the launch stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample on the host cores
+and reports the GPU result's error against it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 4096
+ORDER = 4
+OPS_PER_STEP = 4
+BYTES_PER_DOF_PASS = 16
+NFIELDS = 4  # rotate independent fields so one pass never re-reads what the last few wrote
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("sc_kernels.hip", "sc_device.h"):
+        with open(os.path.join(ROOT, "paper_2007_03041_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries (None if stale or absent)."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, torch, grid, pde_kw):
+    """The FP64 oracle on a bounded sample (2 full-size steps from the benchmark's initial data),
+    timed on the host cores; the GPU runs the same 2 steps and its error against the oracle is
+    reported relative to max|u|."""
+    import numpy as np
+
+    import oracle
+    from paper_2007_03041_amd import workloads as W
+
+    steps = 2
+    u0 = W.fourier_field(N, N)
+    og = oracle.make_grid((N, N), (0.0, 0.0), (2 * math.pi, 2 * math.pi))
+    t0 = time.perf_counter()
+    ref = oracle.time_step(og, (1.0, 1.0), 1.0, 1.0, pde_kw["dt"], ORDER, steps, u0, split=True)
+    t = time.perf_counter() - t0
+    u = torch.from_numpy(u0).to("cuda")
+    sc.time_step(u, grid, steps, **pde_kw)
+    torch.cuda.synchronize()
+    err = float(np.abs(u.cpu().numpy() - ref).max() / np.abs(ref).max())
+    return {
+        "value": N * N * OPS_PER_STEP * steps / t,
+        "unit": "DOF*applications/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} full-size time steps of the benchmark workload ({N}x{N}, FP64), "
+                  f"{t:.2f} s wall",
+        "gpu_max_rel_err_vs_oracle": err,
+    }
+
+
+def calibrate_copy(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE readings."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes_each_way": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2007_03041_amd as sc
+    from paper_2007_03041_amd import workloads as W
+
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
+
+    sc.load()
+    L = 2 * math.pi
+    dx = L / N
+    grid = sc.Grid((N, N), (0.0, 0.0), (L, L))
+    pde_kw = dict(c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dx, order=ORDER, split=True)
+    pde = sc.make_pde(**pde_kw)
+    fields = [W.fourier_field(N, N, device="cuda") for _ in range(NFIELDS)]
+    stepper = sc.TimeStepper(grid, pde)
+
+    for i in range(args.warmup):
+        stepper.step(fields[i % NFIELDS], 1)
+    torch.cuda.synchronize()
+
+    sc.timing_reset()
+    sc.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stepper.step(fields[i % NFIELDS], 1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sc.timing_enable(False)
+    ktimes = sc.timing_read()
+    sc.timing_reset()
+
+    ms_per_step = 1e3 * t / args.steps
+    dof = N * N
+    value = dof * OPS_PER_STEP / (t / args.steps)
+
+    # dominant kernel: the one with the largest total time in the timed region
+    name, (tot_ms, cnt) = max(ktimes.items(), key=lambda kv: kv[1][0])
+    avg_s = tot_ms / cnt / 1e3
+    # one fused or apply launch reads the operand and writes the result over every DOF once;
+    # an aggregate-only launch (chunked passes) reads it once and writes per-chunk scalars
+    alg_bytes = (8 if "agg" in name else BYTES_PER_DOF_PASS) * dof
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = load_traffic(name)
+
+    out = {
+        "metric": "DOF updates/s per L^{-1}/D application on 1 GPU; % HBM roofline; error vs FP64",
+        "value": value,
+        "unit": "DOF*applications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2-D linear advection-diffusion, 4096x4096 periodic on [0,2pi]^2, FP64, "
+                        "order-4 local quadrature, dimension-split x then y, dt=dx, beta=1, "
+                        "8 seeded Fourier modes",
+            "grid": [N, N],
+            "operator_applications_per_step": OPS_PER_STEP,
+            "fields_rotated": NFIELDS,
+            "paper_metric_dof_per_s": dof / (t / args.steps),
+            "kernel_ms": {k: v[0] / v[1] for k, v in ktimes.items()},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": name,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "mean_launch_ms": avg_s * 1e3,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, torch, grid, pde_kw)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -101,7 +101,11 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int ord
  *   u <- u - sum_d |c_d| dt alpha_d D_{R or L, d}[u] - sum_d nu_diff dt alpha_nu^2 D_{0,d}[u]
  * with alpha_d = beta/(|c_d| dt) (D_R if c_d > 0, D_L if c_d < 0) and alpha_nu = beta/sqrt(nu dt)
  * (Sec. 2.1 alpha choices; Sec. 2.2 first-order representations; Sec. 2.5 explicit coupling).
- * Dirichlet axes hold u = 0 at both ends.  nn_policy applies the nearest-neighbour time-step bound
+ * split = 0: all D terms act on u^n and are summed (the coupling of Sec. 2.5; its amplification
+ * of grid-scale modes is 1 - d (beta + beta^2) with both operators on d axes, so |.| <= 1 needs
+ * d (beta + beta^2) <= 2).  split = 1: dimension splitting -- the same 1-D step applied to each
+ * axis in turn, x then y then z, each acting on the previous one's result (per-axis factors of
+ * modulus <= 1 at beta = 1).  Dirichlet axes hold u = 0 at both ends.  nn_policy applies the nearest-neighbour time-step bound
  * of Sec. 3.1 with tolerance nn_eps over blocks of length block_len (0 = the whole axis):
  * 0 = ignore, 1 = reduce dt to the bound, 2 = fail with SC_ERR_ARG if dt exceeds it. */
 typedef struct {
@@ -113,6 +117,8 @@ typedef struct {
     int32_t nn_policy;
     double nn_eps;    /* 0 -> 1e-16 */
     double block_len; /* 0 -> axis length */
+    int32_t split;    /* 0 additive (unsplit), 1 dimension-split x, y, z */
+    int32_t reserved; /* must be 0 */
 } sc_linear_pde;
 
 sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps, void *u,

@@ -46,7 +46,7 @@ class _Grid(ctypes.Structure):
 
 class _Pde(ctypes.Structure):
     _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double),
-                ("dt", c_double), ("order", c_int32)]
+                ("dt", c_double), ("order", c_int32), ("split", c_int32)]
 
 
 _lib = None
@@ -194,12 +194,12 @@ def apply_D_partial_sum(grid: _Grid, dim, op, order, alpha, k, scale, v, g=None)
     return out
 
 
-def time_step(grid: _Grid, c, nu_diff, beta, dt, order, nsteps, u):
+def time_step(grid: _Grid, c, nu_diff, beta, dt, order, nsteps, u, split=False):
     u = _f64(u).copy()
     p = _Pde()
     for e in range(3):
         p.c[e] = c[e] if e < len(c) else 0.0
-    p.nu_diff, p.beta, p.dt, p.order = nu_diff, beta, dt, order
+    p.nu_diff, p.beta, p.dt, p.order, p.split = nu_diff, beta, dt, order, int(bool(split))
     _check(_load().sco_time_step(ctypes.byref(grid), ctypes.byref(p), nsteps, _p(u)),
            "time_step")
     return u

@@ -360,6 +360,7 @@ int sco_time_step(const sco_grid *g, const sco_pde *p, int nsteps, double *u)
     for (int step = 0; step < nsteps && rc == 0; ++step) {
         memcpy(acc, u, sizeof(double) * tot);
         for (int dim = 0; dim < g->ndim && rc == 0; ++dim) {
+            if (p->split && dim > 0) memcpy(u, acc, sizeof(double) * tot); /* next axis acts on the result */
             double c = p->c[dim];
             if (c != 0.0) {
                 /* alpha = beta / (|c| dt); c > 0 uses the left-biased d/dx ~ alpha D_R, c < 0 the

@@ -69,13 +69,16 @@ int sco_apply_D_partial_sum(const sco_grid *g, int dim, int op, int order, doubl
                             double scale, const double *gvals, const double *v, double *out);
 
 /* Forward-Euler step of u_t + c . grad u = nu_diff * lap u with D operators (Sec. 2.1 alpha
- * choices, Sec. 2.5 coupling, first-order representations); Dirichlet axes use g = 0. */
+ * choices, Sec. 2.5 coupling, first-order representations); Dirichlet axes use g = 0.
+ * split = 0: every axis' D terms act on u^n and are added (the explicit coupling of Sec. 2.5);
+ * split = 1: dimension splitting, one such 1-D step per axis in turn (x, then y, then z). */
 typedef struct {
     double c[3];
     double nu_diff;
     double beta;
     double dt;
     int32_t order;
+    int32_t split;
 } sco_pde;
 int sco_time_step(const sco_grid *g, const sco_pde *p, int nsteps, double *u);
 

@@ -46,7 +46,7 @@ class sc_grid(ctypes.Structure):
 class sc_linear_pde(ctypes.Structure):
     _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double), ("dt", c_double),
                 ("order", c_int32), ("nn_policy", c_int32), ("nn_eps", c_double),
-                ("block_len", c_double)]
+                ("block_len", c_double), ("split", c_int32), ("reserved", c_int32)]
 
 
 @dataclass
@@ -238,12 +238,13 @@ def apply_D_partial_sum(v, grid: Grid, dim: int, op: str, order: int, alpha: flo
 
 
 def make_pde(c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6, nn_policy=0, nn_eps=0.0,
-             block_len=0.0) -> sc_linear_pde:
+             block_len=0.0, split=False) -> sc_linear_pde:
     p = sc_linear_pde()
     for e in range(3):
         p.c[e] = float(c[e]) if e < len(c) else 0.0
     p.nu_diff, p.beta, p.dt, p.order = float(nu_diff), float(beta), float(dt), int(order)
     p.nn_policy, p.nn_eps, p.block_len = int(nn_policy), float(nn_eps), float(block_len)
+    p.split, p.reserved = int(bool(split)), 0
     return p
 
 
@@ -265,9 +266,9 @@ class TimeStepper:
 
 
 def time_step(u, grid: Grid, nsteps: int, c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6,
-              nn_policy=0, nn_eps=0.0, block_len=0.0):
+              nn_policy=0, nn_eps=0.0, block_len=0.0, split=False):
     """Advance u (in place) by ``nsteps`` first-order steps of u_t + c.grad u = nu_diff lap u."""
-    pde = make_pde(c, nu_diff, beta, dt, order, nn_policy, nn_eps, block_len)
+    pde = make_pde(c, nu_diff, beta, dt, order, nn_policy, nn_eps, block_len, split)
     return TimeStepper(grid, pde, u.device).step(u, nsteps)
 
 

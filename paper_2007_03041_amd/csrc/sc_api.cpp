@@ -415,6 +415,7 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
     if (!(pde->dt > 0.0) || !(pde->beta > 0.0) || !(pde->nu_diff >= 0.0))
         return fail(SC_ERR_ARG, "dt and beta must be > 0 and nu_diff >= 0");
     if (pde->nn_policy < 0 || pde->nn_policy > 2) return fail(SC_ERR_ARG, "nn_policy must be 0, 1 or 2");
+    if (pde->split != 0 && pde->split != 1) return fail(SC_ERR_ARG, "split must be 0 or 1");
     double dt = pde->dt;
     if (pde->nn_policy != 0) {
         const double bound = nn_bound(grid, pde);
@@ -458,12 +459,20 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
         bool first = true;
         for (int d = 0; d < grid->ndim; ++d) {
             if (!nops[d]) continue;
+            if (pde->split) {
+                // one 1-D step on the current state: nxt = cur + sum_ops scale * D[cur]
+                s = run_pass(grid, d, pde->order, ops[d], nops[d], cur, nullptr, 1, nxt, nullptr, rest, rest_bytes, st);
+                if (s != SC_OK) return s;
+                std::swap(cur, nxt);
+                continue;
+            }
+            // unsplit: every axis reads u^n (cur); nxt accumulates u^n + all D terms
             s = run_pass(grid, d, pde->order, ops[d], nops[d], cur, first ? nullptr : nxt, first ? 1 : 2, nxt, nullptr,
                          rest, rest_bytes, st);
             if (s != SC_OK) return s;
             first = false;
         }
-        if (!first) std::swap(cur, nxt);
+        if (!pde->split && !first) std::swap(cur, nxt);
     }
     if (cur != u) {
         hipError_t e = hipMemcpyAsync(u, cur, fbytes, hipMemcpyDeviceToDevice, st);

@@ -60,6 +60,41 @@ def test_two_dimensional_step_matches_mode_symbols(order):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("order", [4, 6])
+def test_dimension_split_step_is_product_of_axis_symbols(order):
+    """Split form: u <- (1-D step along y)(1-D step along x) u, so each mode is multiplied by the
+    product of the per-axis factors 1 - beta(1 - s_adv) - beta^2 (1 - s_0)."""
+    n = (40, 36)
+    L = (2 * np.pi, 2 * np.pi)
+    dxs = [L[d] / n[d] for d in range(2)]
+    X, Y = np.meshgrid(np.arange(n[0]) * dxs[0], np.arange(n[1]) * dxs[1])
+    modes = [((2, 1), 0.6, 0.4), ((-5, 3), 0.3, 1.7)]
+    c, nu_diff, beta, dt, steps = (1.0, 0.8), 1.0, 1.0, 0.1, 4
+    u0 = sum(a * np.cos(k[0] * X + k[1] * Y + ph) for k, a, ph in modes)
+    g = oracle.make_grid(n, (0, 0), L)
+    got = oracle.time_step(g, c, nu_diff, beta, dt, order, steps, u0, split=True)
+    ref = 0.0
+    for k, a, ph in modes:
+        S = 1.0 + 0j
+        for d in range(2):
+            S *= _step_symbol((k[d],), (dxs[d],), (c[d],), nu_diff, beta, dt, order)
+        ref = ref + np.real(a * np.exp(1j * ph) * S ** steps * np.exp(1j * (k[0] * X + k[1] * Y)))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_grid_scale_amplification_of_the_two_forms():
+    """Nyquist mode with advection and diffusion on both axes at beta = 1: the unsplit (additive)
+    factor is close to 1 - 2(1 + 1) = -3, the split factor is a product of two factors of modulus <= 1."""
+    N = 64
+    dx = 2 * np.pi / N
+    unsplit = _step_symbol((N // 2, N // 2), (dx, dx), (1.0, 1.0), 1.0, 1.0, dx, 4)
+    split = _step_symbol((N // 2,), (dx,), (1.0,), 1.0, 1.0, dx, 4) ** 2
+    assert abs(unsplit) > 2.5
+    assert abs(split) <= 1.0 + 1e-12
+    for k in range(N // 2 + 1):
+        assert abs(_step_symbol((k,), (dx,), (1.0,), 1.0, 1.0, dx, 4)) <= 1.0 + 1e-12
+
+
 def test_three_dimensional_step_matches_mode_symbols():
     n = (12, 10, 9)
     L = (1.0, 2.0, 1.5)
