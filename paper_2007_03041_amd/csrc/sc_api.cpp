@@ -8,7 +8,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -118,46 +120,89 @@ bool overlap(const void *a, const void *b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// Kernel variant for a line pass along an axis of n points (contiguous or strided).  The choice
+// can be overridden for tuning with SC_VARIANT_CONTIG / SC_VARIANT_STRIDED (variant ids).
+int pick_variant(bool contig, int64_t n)
+{
+    const char *env = std::getenv(contig ? "SC_VARIANT_CONTIG" : "SC_VARIANT_STRIDED");
+    if (env && *env) {
+        const int id = std::atoi(env);
+        if (id >= 0 && id < scx::num_variants() && scx::variant(id).contig == contig) return id;
+    }
+    if (contig) {
+        if (n <= 256) return 0;
+        if (n <= 1024) return 1;
+        if (n <= 4096) return 2;
+        return 3;
+    }
+    if (n <= 256) return 4;
+    if (n <= 512) return 5;
+    return 6;  // 16 lines x 1024; longer lines chunked
+}
+
+// decay from the start of the last real wave-part of a tile to the tile's last real point
+double last_part_decay(double nu, int64_t n_loc, const scx::Variant &V)
+{
+    const int64_t span = (int64_t)V.S * V.GW();
+    const int64_t part_last = ((n_loc - 1) / V.S) / V.GW();
+    return std::exp(-nu * (double)(n_loc - part_last * span));
+}
+
 // Per-(axis, operator, alpha) constants for the variant chosen for the pass.
-void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, int variant,
-             int64_t chunk, double scale, int k)
+void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid, double scale, int k)
 {
     std::memset(P, 0, sizeof(*P));
+    const scx::Variant &V = scx::variant(vid);
     const int H = order / 2;
     const double nu = alpha * ax.dx;
     int eta[8];
     // interior: window offset j <-> node x_{i-H+j} <-> eta = H - j (J_R); J_L uses the mirror
     for (int j = 0; j < order; ++j) eta[j] = H - j;
     scx::quad_weights(nu, order, eta, P->wR);
-    // Dirichlet one-sided stencils (nodes 0..order-1 at the left end, n-order..n-1 at the right)
-    for (int q = 0; q + 1 < H; ++q) {
-        int i = q + 1;  // J_R at i, nodes j: eta = i - j
-        for (int j = 0; j < order; ++j) eta[j] = i - j;
-        scx::quad_weights(nu, order, eta, P->bRl[q]);
-        // J_R at i = n-H+1+q with nodes n-order+j: eta = (order - H + 1 + q) - j
-        for (int j = 0; j < order; ++j) eta[j] = (order - H + 1 + q) - j;
-        scx::quad_weights(nu, order, eta, P->bRr[q]);
-        // J_L at i = q with nodes j: eta = j - q
-        for (int j = 0; j < order; ++j) eta[j] = j - q;
-        scx::quad_weights(nu, order, eta, P->bLl[q]);
-        // J_L at i = n-H+q with nodes n-order+j: eta = j - order + H - q
-        for (int j = 0; j < order; ++j) eta[j] = j - order + H - q;
-        scx::quad_weights(nu, order, eta, P->bLr[q]);
+    const int S = V.S;
+    // segment totals as linear functionals of the window (S + order values):
+    //   sum_t d^{S-1-t} J_R[t] = sum_w kR[w] win[w],  J_R[t] = sum_j wR[j] win[t+j]
+    //   sum_t d^t J_L[t]       = sum_w kL[w] win[w],  J_L[t] = sum_j wR[order-1-j] win[t+1+j]
+    for (int w = 0; w < S + order; ++w) {
+        double kr = 0.0, kl = 0.0;
+        for (int j = 0; j < order; ++j) {
+            const int tr = w - j;
+            if (tr >= 0 && tr < S) kr += P->wR[j] * std::exp(-nu * (double)(S - 1 - tr));
+            const int tl = w - 1 - j;
+            if (tl >= 0 && tl < S) kl += P->wR[order - 1 - j] * std::exp(-nu * (double)tl);
+        }
+        P->kR[w] = kr;
+        P->kL[w] = kl;
     }
-    const int S = scx::variant_S(variant);
-    const int GW = scx::variant_GW(variant);
+    const int64_t C = V.C();
+    const int64_t nch = (ax.n + C - 1) / C;
     P->d = std::exp(-nu);
     P->nu = nu;
     for (int t = 0; t <= scx::MAXS; ++t) P->dpow[t] = std::exp(-nu * t);
-    for (int j = 0; j < 8; ++j) P->dseg[j] = std::exp(-nu * (double)S * (double)(1 << j));
-    P->dpart = std::exp(-nu * (double)S * (double)GW);
-    P->dchunk = std::exp(-nu * (double)chunk);
+    for (int j = 0; j < 12; ++j) P->dseg[j] = std::exp(-nu * (double)S * (double)(1 << j));
+    P->dpart = std::exp(-nu * (double)S * (double)V.GW());
+    P->dchunk = std::exp(-nu * (double)C);
+    P->dlp_full = last_part_decay(nu, std::min<int64_t>(ax.n, C), V);
+    P->dlp_last = last_part_decay(nu, ax.n - (nch - 1) * C, V);
     const double x = nu * (double)ax.ncells;  // alpha (b - a)
     P->mu = std::exp(-x);
     P->inv1mmu = 1.0 / (-std::expm1(-x));
     P->scale = scale;
     P->op = op;
     P->k = k;
+}
+
+// Lagrange basis on nodes 0..order-1 evaluated at -m, m = 1..order/2: the values that extend a
+// Dirichlet line beyond its ends by the interpolant of its `order` end values.
+void fill_ext(scx::PassArgs *a, int order)
+{
+    for (int m = 1; m <= order / 2; ++m)
+        for (int j = 0; j < order; ++j) {
+            double l = 1.0;
+            for (int q = 0; q < order; ++q)
+                if (q != j) l *= (double)(-m - q) / (double)(j - q);
+            a->ext[m - 1][j] = l;
+        }
 }
 
 struct OpSpec {
@@ -176,8 +221,7 @@ size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops)
 
 int64_t nchunks_for(const Axis &ax)
 {
-    int variant;
-    const int64_t C = scx::pick_chunk(ax.stride == 1, ax.n, &variant);
+    const int64_t C = scx::variant(pick_variant(ax.stride == 1, ax.n)).C();
     return (ax.n + C - 1) / C;
 }
 
@@ -187,8 +231,8 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
                    hipStream_t st)
 {
     const Axis ax = axis_of(g, dim);
-    int variant;
-    const int64_t C = scx::pick_chunk(ax.stride == 1, ax.n, &variant);
+    const int vid = pick_variant(ax.stride == 1, ax.n);
+    const int64_t C = scx::variant(vid).C();
     scx::PassArgs a;
     std::memset(&a, 0, sizeof(a));
     a.v = v;
@@ -203,12 +247,21 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     a.bc = ax.bc;
     a.acc_mode = acc_mode;
     a.nops = nops;
-    for (int o = 0; o < nops; ++o)
-        fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, variant, C, ops[o].scale, ops[o].k);
+    fill_ext(&a, order);
+    bool multi = false;
+    for (int o = 0; o < nops; ++o) {
+        fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, vid, ops[o].scale, ops[o].k);
+        multi = multi || ops[o].k > 1;
+    }
+    if (multi && (nops != 1 || a.nchunks != 1 || ax.bc != SC_BC_PERIODIC || acc_mode != 0))
+        return fail(SC_ERR_UNSUPPORTED, "internal: fused powers of D need one periodic operator on whole lines");
+    const int64_t tiles = (ax.nlines + scx::variant(vid).TC - 1) / scx::variant(vid).TC;
+    if (tiles * a.nchunks > (int64_t)INT32_MAX) return fail(SC_ERR_SHAPE, "too many lines for one launch");
+    const bool contig = scx::variant(vid).contig;
     hipError_t e;
     if (a.nchunks == 1) {
-        e = timed("line_pass_fused", st, [&](const char **nm) {
-            return scx::launch_line_pass(a, order, variant, scx::LMODE_FUSED, st, nm);
+        e = timed(contig ? "line_pass_fused_x" : "line_pass_fused_yz", st, [&](const char **) {
+            return scx::launch_line_pass(a, order, vid, scx::LMODE_FUSED, multi, st);
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         return SC_OK;
@@ -218,14 +271,14 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     const int64_t ent = (int64_t)nops * ax.nlines * a.nchunks;
     a.agg = (double *)wsp;
     a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
-    e = timed("line_pass_agg", st, [&](const char **nm) {
-        return scx::launch_line_pass(a, order, variant, scx::LMODE_AGG, st, nm);
+    e = timed(contig ? "line_pass_agg_x" : "line_pass_agg_yz", st, [&](const char **) {
+        return scx::launch_line_pass(a, order, vid, scx::LMODE_AGG, false, st);
     });
     if (e == hipSuccess)
         e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, C, st); });
     if (e == hipSuccess)
-        e = timed("line_pass_apply", st, [&](const char **nm) {
-            return scx::launch_line_pass(a, order, variant, scx::LMODE_APPLY, st, nm);
+        e = timed(contig ? "line_pass_apply_x" : "line_pass_apply_yz", st, [&](const char **) {
+            return scx::launch_line_pass(a, order, vid, scx::LMODE_APPLY, false, st);
         });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return SC_OK;
@@ -285,7 +338,8 @@ sc_status sc_local_quad(const sc_grid *grid, int dim, int order, double alpha, c
     a.ncells = ax.ncells;
     a.bc = ax.bc;
     a.nops = 1;
-    fill_op(&a.ops[0], SC_OP_0, order, alpha, ax, 0, 1, 1.0, 0);
+    fill_ext(&a, order);
+    fill_op(&a.ops[0], SC_OP_0, order, alpha, ax, 0, 1.0, 0);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = timed("local_quad", st, [&](const char **) { return scx::launch_local_quad(a, order, JL, JR, st); });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));

@@ -1,26 +1,33 @@
 // sc_kernels.hip -- gfx950 kernels of the successive-convolution fast summation.
 //
-// One pass applies up to two operators L_op^{-1} (or their D partial sums) along one axis of a
-// dense array, line by line (Sec. 2.2: the directions stay uncoupled).  Work decomposition:
+// One pass applies up to two operators L_op^{-1} (or D = I - L_op^{-1} and its partial sums) along
+// one axis of a dense array, line by line (Sec. 2.2: the directions stay uncoupled).
 //
-//   workgroup  = a tile of TC lines x one chunk of C = G*S points of each line (+ halo of order/2)
-//   thread     = one segment of S consecutive points of one line (G segments per line)
+//   workgroup = a tile of TC lines x one chunk of C = G*S points of each line (+ order/2 halo)
+//   thread    = one segment of S consecutive points of one line (G segments per line)
 //
-// Steps inside a workgroup (all in registers / LDS, one HBM read of the operand, one write):
-//   1. coalesced load of the tile into LDS in [line][point] layout -- along x the lanes run along
-//      the line, along y/z across adjacent lines, so y/z tiles are transposed through LDS;
-//   2. each thread forms the local integrals J_R, J_L of its segment (Sec. 2.4, eqs. (JR), (JL))
-//      from a register window, with one-sided stencils at Dirichlet ends;
-//   3. each thread sweeps its segment serially (the O(N) recurrences of Sec. 2.4);
-//   4. the segments are combined by a first-order linear-recurrence scan over (decay, value)
-//      pairs: Kogge-Stone with wavefront shuffles inside a wave (decay d^{S 2^j}), LDS between the
-//      waves of a line, and chunk carries between workgroups (Sec. 3, eqs. (Left-/Right-moving
-//      integral DD): a block's integral = its local sweep + attenuated neighbour contributions);
-//   5. the line totals give the boundary constants A, B in FP64 (Sec. 2.3 periodic constants;
-//      Dirichlet end values through the 2x2 system whose inverse has the form of Sec. 3.3);
-//   6. combine L_0^{-1} = (I_L + I_R)/2 + A e^{-alpha(x-a)} + B e^{-alpha(b-x)} (Sec. 2.1, 2.4),
-//      optionally D = I - L^{-1} and its successive powers (Sec. 2.2), times a scale, plus an
-//      accumulator (the explicit update of Sec. 2.5), and store through LDS.
+// Per workgroup, with one HBM read of the operand and one write of the result:
+//   1. coalesced load of the tile into LDS in [line][point] layout (one pad element per segment
+//      against bank conflicts).  Along x the lanes run along the line; along y/z they run across TC
+//      adjacent lines, so y/z tiles are transposed through LDS.  Each thread then holds the window
+//      of S + order operand values around its segment in registers.
+//   2. segment totals of the two sweeps (Sec. 2.4 recurrences).  In the interior they are linear
+//      in the window, so each is one dot product with coefficients precomputed on the host (kR,
+//      kL); segments at line ends and in the padding use the point-by-point local integrals of
+//      Sec. 2.4, eqs. (JR), (JL).  A Dirichlet line's one-sided end stencils are realised by
+//      extending the line beyond each end with the interpolant of its end values, so the centred
+//      stencil integrates the same polynomial there.
+//   3. the segments are combined by a first-order linear-recurrence scan over (decay, value) pairs:
+//      Kogge-Stone with wavefront shuffles inside a wave (decay d^{S 2^j}) and one LDS exchange
+//      between the waves of a line (Sec. 3, eqs. (Left-/Right-moving integral DD): a block's
+//      integral = its own sweep + attenuated contributions of the others).  Lines longer than one
+//      tile are chunked: an aggregate launch, a carry launch and an apply launch.
+//   4. the line totals give the boundary constants in FP64 (Sec. 2.3 periodic constants; Dirichlet
+//      end values through the 2x2 system whose inverse has the form of Sec. 3.3).
+//   5. each thread re-sweeps its segment from the exact carries: the forward sweep adds its share
+//      of the result, the backward sweep the rest (L_0^{-1} = (I_L + I_R)/2 + A e^{-alpha(x-a)}
+//      + B e^{-alpha(b-x)} is linear in the two sweeps), scaled, as D = I - L^{-1} (Sec. 2.2) and
+//      plus an accumulator (the explicit update of Sec. 2.5).  Only the S outputs stay in registers.
 //
 // The boundary terms are folded in as A' d^i and B' d^{N-i} with A' = I_R(b)/(1-mu),
 // B' = I_L(a)/(1-mu) for periodic lines (for L_0 these are twice the paper's A, B because the
@@ -29,6 +36,7 @@
 #include <stdint.h>
 
 #include "sc_device.h"
+#include "sc_launch.h"
 
 namespace scx {
 
@@ -43,14 +51,22 @@ __device__ __forceinline__ double shfl_down_d(double x, int delta)
     return __shfl_down(x, (unsigned)delta, WAVE);
 }
 
-// d^{S m} for 0 <= m < 2^8 from the binary powers d^{S 2^j}
+// d^{S m} for 0 <= m < 2^12 from the binary powers d^{S 2^j}
 __device__ __forceinline__ double dseg_pow(const OpArgs &P, int m)
 {
     double r = 1.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 12; ++j)
         if ((m >> j) & 1) r *= P.dseg[j];
     return r;
+}
+
+// A e^{-nu m} for an integer distance m >= 0, skipping exp when it underflows or A == 0
+__device__ __forceinline__ double decayed(double A, double nu, int64_t m)
+{
+    if (A == 0.0 || m < 0) return 0.0;
+    const double x = nu * (double)m;
+    return x > 745.0 ? 0.0 : A * exp(-x);
 }
 
 template <typename T>
@@ -59,51 +75,31 @@ __device__ __forceinline__ T ldg(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-// Dirichlet one-sided local integrals of point i (absolute index) of the line at `base`.
+// Value at point p of the line at `base`: periodic wrap, or for Dirichlet lines the extension of
+// the end interpolant to the order/2 points beyond each end (PassArgs::ext).
 template <typename T, int ORDER>
-__device__ double dirichlet_JR(const OpArgs &P, const T *v, int64_t base, int64_t stride,
-                               int64_t n, int64_t i, double interior)
+__device__ __forceinline__ T line_value(const PassArgs &a, const T *v, int64_t base, int64_t p)
 {
-    constexpr int H = ORDER / 2;
-    if (i == 0) return 0.0;
-    if (i <= H - 1) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < ORDER; ++j) s += P.bRl[i - 1][j] * (double)v[base + j * stride];
-        return s;
+    const int64_t n = a.n;
+    if (a.bc == 0) {
+        if (p < 0) p += n;
+        if (p >= n) p -= n;
+        if (p < 0 || p >= n) {
+            p %= n;
+            if (p < 0) p += n;
+        }
+        return ldg(v + base + p * a.stride);
     }
-    if (i >= n - H + 1) {
-        double s = 0.0;
-        const int q = (int)(i - (n - H + 1));
+    if (p >= 0 && p < n) return ldg(v + base + p * a.stride);
+    const int m = p < 0 ? (int)(-p) : (int)(p - n + 1);  // distance beyond the end, 1..order/2
+    if (m > ORDER / 2) return T(0);
+    double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < ORDER; ++j)
-            s += P.bRr[q][j] * (double)v[base + (n - ORDER + j) * stride];
-        return s;
+    for (int j = 0; j < ORDER; ++j) {
+        const int64_t node = p < 0 ? j : n - 1 - j;
+        s = fma(a.ext[m - 1][j], (double)ldg(v + base + node * a.stride), s);
     }
-    return interior;
-}
-
-template <typename T, int ORDER>
-__device__ double dirichlet_JL(const OpArgs &P, const T *v, int64_t base, int64_t stride,
-                               int64_t n, int64_t i, double interior)
-{
-    constexpr int H = ORDER / 2;
-    if (i == n - 1) return 0.0;
-    if (i <= H - 2) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < ORDER; ++j) s += P.bLl[i][j] * (double)v[base + j * stride];
-        return s;
-    }
-    if (i >= n - H) {
-        double s = 0.0;
-        const int q = (int)(i - (n - H));
-#pragma unroll
-        for (int j = 0; j < ORDER; ++j)
-            s += P.bLr[q][j] * (double)v[base + (n - ORDER + j) * stride];
-        return s;
-    }
-    return interior;
+    return (T)s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -116,26 +112,41 @@ __device__ double dirichlet_JL(const OpArgs &P, const T *v, int64_t base, int64_
 //           false: strided axis (lanes run across TC adjacent lines)
 //   MODE    FUSED: whole line in the tile; AGG: write chunk aggregates; APPLY: use chunk carries
 //   NT      threads per workgroup
+//   NOPS    operators applied to the same operand (1 or 2)
+//   MULTI   partial sums with k > 1 (FUSED, periodic, one operator): the new operand of each
+//           power is shared through the tile
 // ------------------------------------------------------------------------------------------
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT>
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI>
 __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
 {
     constexpr int H = ORDER / 2;
+    constexpr int NWIN = S + ORDER;                  // window: points seg0-H .. seg0+S+H-1
     constexpr int G = NT / TC;                       // segments per line in the tile
     constexpr int C = G * S;                         // chunk length
     constexpr int W = C + 2 * H;                     // tile points per line incl. halos
-    constexpr int LS = W | 1;                        // odd LDS line stride (bank spread)
+    constexpr int LS = (W + W / S + 1) | 1;          // padded, odd LDS line stride
     constexpr int GW = CONTIG ? (G < WAVE ? G : WAVE) : (WAVE / TC);  // segments per wave-part
     constexpr int NP = G / GW;                       // wave-parts per line
     constexpr int SL = CONTIG ? 1 : TC;              // lane distance between adjacent segments
     static_assert(G * TC == NT, "tile shape");
-    static_assert(S <= MAXS, "segment too long");
+    static_assert(S <= MAXS && NWIN <= MAXWIN, "segment too long");
+    static_assert(!MULTI || (MODE == MODE_FUSED && NOPS == 1), "powers of D are fused for one operator on whole lines");
 
     __shared__ T tile[TC * LS];
     __shared__ int64_t lbase[TC];
-    __shared__ double part_f[TC][NP];
-    __shared__ double part_b[TC][NP];
-    __shared__ double tot[TC][3];
+    __shared__ double xf_s[NOPS][TC][NP];   // per wave-part totals of the forward sweep
+    __shared__ double xb_s[NOPS][TC][NP];   //                     ... of the backward sweep
+    __shared__ double j0_s[NOPS][TC];       // J_R at x_0 (periodic: the wrapped last cell)
+    __shared__ double cf_s[NOPS][TC][NP];   // forward carry into each wave-part
+    __shared__ double cb_s[NOPS][TC][NP];   // backward carry into each wave-part
+    __shared__ double ab_s[NOPS][TC][3];    // A' d^{cstart}, B' d^{N-(cstart+C-1)}, B' (see below)
+    __shared__ double pw_s[NOPS][GW + 1];   // d^{S m}, m = 0..GW
+    __shared__ double pp_s[NOPS][NP + 1];   // d^{S GW p}, p = 0..NP
 
     const int tid = threadIdx.x;
     const int c = CONTIG ? tid / G : tid % TC;
@@ -157,262 +168,429 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
         if (L < a.nlines) b = (L / a.stride) * a.stride * n + (L % a.stride);
         lbase[tid] = b;
     }
+    // decay tables (binary powers, computed once per workgroup)
+    for (int e = tid; e < NOPS * (GW + 1 + NP + 1); e += NT) {
+        const int o = e / (GW + 1 + NP + 1), m = e % (GW + 1 + NP + 1);
+        if (m <= GW)
+            pw_s[o][m] = dseg_pow(a.ops[o], m);
+        else
+            pp_s[o][m - GW - 1] = dseg_pow(a.ops[o], (m - GW - 1) * GW);
+    }
     __syncthreads();
 
-    // 1. tile load (periodic halos wrap, Dirichlet halos are zero and never used)
-    for (int e = tid; e < TC * W; e += NT) {
-        const int cc = CONTIG ? e / W : e % TC;
-        const int q = CONTIG ? e % W : e / TC;
-        T val = T(0);
-        if (line0 + cc < a.nlines) {
-            int64_t p = cstart - H + q;
-            bool ok = true;
-            if (a.bc == 0) {
-                if (p < 0) p += n;
-                if (p >= n) p -= n;
-                if (p >= n) p %= n;
-            } else {
-                ok = (p >= 0 && p < n);
+    // 1. tile load: all loads of a thread are issued before any LDS write; periodic halos wrap,
+    //    Dirichlet halos are filled from the end interpolant afterwards
+    {
+        constexpr int FILL = (TC * W + NT - 1) / NT;
+        const int ni = (int)n;
+        const bool wrap_many = (a.bc == 0) && (ni < C + 2 * H);
+        T vals[FILL];
+        if (CONTIG && TC == 1) {
+            // element e = tid + k NT is point p = cstart - H + e of the one line of the tile
+            const int p0 = (int)cstart - H + tid;
+            const T *rowp = v + lbase[0] + p0;
+            const bool lok = line0 < a.nlines;
+#pragma unroll
+            for (int k = 0; k < FILL; ++k) {
+                const int e = tid + k * NT;
+                const int p = p0 + k * NT;
+                T val = T(0);
+                if (lok && e < W) {
+                    if (p >= 0 && p < ni) {
+                        val = ldg(rowp + k * NT);
+                    } else if (a.bc == 0) {
+                        int pw = p;
+                        if (wrap_many) {
+                            pw %= ni;
+                            if (pw < 0) pw += ni;
+                        } else {
+                            pw = p < 0 ? p + ni : p - ni;
+                        }
+                        val = ldg(v + lbase[0] + pw);
+                    }
+                }
+                vals[k] = val;
             }
-            if (ok) val = ldg(v + lbase[cc] + p * a.stride);
+        } else {
+            const int64_t st = CONTIG ? 1 : a.stride;  // contiguous variants only run on stride-1 axes
+            const int c0 = (int)cstart - H;
+#pragma unroll
+            for (int k = 0; k < FILL; ++k) {
+                const int e = tid + k * NT;
+                const int cc = CONTIG ? e / W : e % TC;
+                const int q = CONTIG ? e % W : e / TC;
+                int p = c0 + q;
+                bool ok = (e < TC * W) && (line0 + cc < a.nlines);
+                if (a.bc == 0) {
+                    if (wrap_many) {
+                        p %= ni;
+                        if (p < 0) p += ni;
+                    } else {
+                        p = (p < 0) ? p + ni : (p >= ni ? p - ni : p);
+                    }
+                } else {
+                    ok = ok && (p >= 0 && p < ni);
+                }
+                vals[k] = ok ? ldg(v + lbase[cc] + (int64_t)p * st) : T(0);
+            }
         }
-        tile[cc * LS + q] = val;
+#pragma unroll
+        for (int k = 0; k < FILL; ++k) {
+            const int e = tid + k * NT;
+            const int cc = CONTIG ? e / W : e % TC;
+            const int q = CONTIG ? e % W : e / TC;
+            if (e < TC * W) tile[cc * LS + q + q / S] = vals[k];
+        }
+    }
+    if (a.bc == 1 && (cstart == 0 || cstart + C + H > n)) {
+        __syncthreads();
+        for (int e = tid; e < TC * 2 * H; e += NT) {
+            const int cc = e / (2 * H), h = e % (2 * H);
+            const int64_t p = (h < H) ? (int64_t)(-1 - h) : n + (h - H);
+            const int64_t q = p - cstart + H;
+            if (line0 + cc < a.nlines && q >= 0 && q < W) {
+                const int qi = (int)q;
+                tile[cc * LS + qi + qi / S] = line_value<T, ORDER>(a, v, lbase[cc], p);
+            }
+        }
     }
     __syncthreads();
 
     const bool line_ok = (line0 + c) < a.nlines;
     const int64_t myline = line0 + c;
-    const int64_t seg0 = cstart + (int64_t)g * S;   // first point of this segment
-    const int64_t mybase = lbase[c];
+    const int64_t seg0 = cstart + (int64_t)g * S;    // first point of this segment
+    const int64_t n_loc = ((cstart + C < n) ? cstart + C : n) - cstart;  // real points in the tile
+    const int s_last = (int)((n_loc - 1) / S);       // segment holding the tile's last real point
+    const int t_last = (int)(n_loc - 1 - (int64_t)s_last * S);
+    const int part_last = s_last / GW;
+    // segments holding x_0 (J_R excluded), the last point (Dirichlet: J_L excluded) or padding
+    const bool edge = (seg0 == 0) || (seg0 + S >= n);
+    const int wbase = c * LS + g * (S + 1);
 
-    T win[S + 2 * H];
+    T win[NWIN];
 #pragma unroll
-    for (int w = 0; w < S + 2 * H; ++w) win[w] = tile[c * LS + g * S + w];
+    for (int w = 0; w < NWIN; ++w) win[w] = tile[wbase + w + w / S];
 
+    // the operand enters the result once: acc_mode 1 adds v, each D = v - L^{-1} v adds scale v
+    double vcoef = (a.acc_mode == 1) ? 1.0 : 0.0;
+    if (!MULTI) {
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o)
+            if (a.ops[o].k >= 1) vcoef += a.ops[o].scale;
+    }
     double outv[S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) outv[t] = 0.0;
+    for (int t = 0; t < S; ++t) outv[t] = vcoef * (double)win[t + H];
 
-    for (int o = 0; o < a.nops; ++o) {
-        const OpArgs &P = a.ops[o];
-        const int kk = P.k > 0 ? P.k : 1;
-        const double d = P.d;
-        for (int it = 0; it < kk; ++it) {
-            // 2. local integrals and 3. serial sweeps of the segment
-            double lR[S], lL[S];
-            double jr0 = 0.0;
-            {
-                double JR[S], JL[S];
-#pragma unroll
-                for (int t = 0; t < S; ++t) {
-                    double sr = 0.0, sl = 0.0;
-#pragma unroll
-                    for (int j = 0; j < ORDER; ++j) {
-                        sr += P.wR[j] * (double)win[t + j];
-                        sl += P.wR[ORDER - 1 - j] * (double)win[t + 1 + j];
-                    }
-                    JR[t] = sr;
-                    JL[t] = sl;
-                }
-                const bool near_end = (seg0 < H) || (seg0 + S + H > n);
-                if (near_end) {
-#pragma unroll
-                    for (int t = 0; t < S; ++t) {
-                        const int64_t i = seg0 + t;
-                        if (i >= n) {
-                            JR[t] = 0.0;
-                            JL[t] = 0.0;
-                        } else if (a.bc == 0) {
-                            if (i == 0) {
-                                jr0 = JR[t];
-                                JR[t] = 0.0;
-                            }
-                        } else {
-                            JR[t] = dirichlet_JR<T, ORDER>(P, v, mybase, a.stride, n, i, JR[t]);
-                            JL[t] = dirichlet_JL<T, ORDER>(P, v, mybase, a.stride, n, i, JL[t]);
-                        }
-                    }
-                }
-                double f = 0.0;
-#pragma unroll
-                for (int t = 0; t < S; ++t) {
-                    f = fma(d, f, JR[t]);
-                    lR[t] = f;
-                }
-                double b = 0.0;
-#pragma unroll
-                for (int t = S - 1; t >= 0; --t) {
-                    b = fma(d, b, JL[t]);
-                    lL[t] = b;
-                }
-            }
+    // per-point rules of edge segments: J_R(x_0) = 0 (the cell left of x_0 is not part of the sweep;
+    // periodic lines add it to I_R(b)), J_L(x_{n-1}) = 0 on Dirichlet lines, nothing past the end
+    auto keepR = [&](int t) { const int64_t i = seg0 + t; return i > 0 && i < n; };
+    auto keepL = [&](int t) { const int64_t i = seg0 + t; return i < n && !(a.bc == 1 && i == n - 1); };
 
-            // 4. scan of the segment totals across the line (decay d^S per segment)
-            double xf = lR[S - 1], xb = lL[0];
+    const int kk = MULTI ? a.ops[0].k : 1;
+    for (int it = 0; it < kk; ++it) {
+        // 2. segment totals of the forward and backward sweeps
+        double aF[NOPS], aB[NOPS], jr0[NOPS];
 #pragma unroll
-            for (int s = 0, kx = 1; kx < GW; ++s, kx <<= 1) {
-                const double yf = shfl_up_d(xf, kx * SL);
-                const double yb = shfl_down_d(xb, kx * SL);
-                if (gl >= kx) xf = fma(P.dseg[s], yf, xf);
-                if (gl + kx < GW) xb = fma(P.dseg[s], yb, xb);
-            }
-            double ef = shfl_up_d(xf, SL);
-            double eb = shfl_down_d(xb, SL);
-            if (gl == 0) ef = 0.0;
-            if (gl == GW - 1) eb = 0.0;
-
-            double cf = 0.0, cb = 0.0;  // carries at the chunk boundaries
-            const int64_t cidx = ((int64_t)o * a.nlines + myline) * nchunks + chunk;
-            if (MODE == MODE_APPLY && line_ok) {
-                cf = a.carry[2 * cidx + 0];
-                cb = a.carry[2 * cidx + 1];
-            }
-            if (NP > 1) {
-                if (gl == GW - 1) part_f[c][part] = xf;
-                if (gl == 0) part_b[c][part] = xb;
-                __syncthreads();
-                for (int p2 = 0; p2 < part; ++p2) cf = fma(P.dpart, cf, part_f[c][p2]);
-                for (int p2 = NP - 1; p2 > part; --p2) cb = fma(P.dpart, cb, part_b[c][p2]);
-                __syncthreads();
-            }
-            const double Ef = fma(dseg_pow(P, gl), cf, ef);           // I_R at seg0 - 1 (no A)
-            const double Eb = fma(dseg_pow(P, GW - 1 - gl), cb, eb);  // I_L at seg0 + S (no B)
-
-            // 5. totals of the line (FUSED) or of the chunk (AGG)
-            double Ap = 0.0, Bp = 0.0;
-            if (MODE != MODE_APPLY) {
-                const int64_t last = (MODE == MODE_FUSED) ? n - 1 : ((cstart + C < n ? cstart + C : n) - 1);
-                if (line_ok && seg0 <= last && last < seg0 + S) {
-                    const int tl = (int)(last - seg0);
-                    double val = 0.0;
+        for (int o = 0; o < NOPS; ++o) {
+            const OpArgs &P = a.ops[o];
+            double sf = 0.0, sb = 0.0, j0 = 0.0;
+            if (!edge) {
+                if (P.op != 0) {
 #pragma unroll
-                    for (int t = 0; t < S; ++t)
-                        if (t == tl) val = fma(P.dpow[t + 1], Ef, lR[t]);
-                    tot[c][0] = val;
+                    for (int w = 0; w < NWIN; ++w) sf = fma(P.kR[w], (double)win[w], sf);
                 }
-                if (g == 0) {
-                    tot[c][1] = fma(P.dpow[S], Eb, lL[0]);
-                    tot[c][2] = jr0;
-                }
-                __syncthreads();
-                const double IRn = tot[c][0], IL0 = tot[c][1], J0 = tot[c][2];
-                __syncthreads();
-                if (MODE == MODE_AGG) {
-                    if (g == 0 && line_ok) {
-                        a.agg[3 * cidx + 0] = IRn;
-                        a.agg[3 * cidx + 1] = IL0;
-                        a.agg[3 * cidx + 2] = J0;
-                    }
-                    continue;  // aggregates only (k == 1 in chunked passes)
-                }
-                if (a.bc == 0) {
-                    Ap = fma(d, IRn, J0) * P.inv1mmu;
-                    Bp = IL0 * P.inv1mmu;
-                } else {
-                    const double ga = (a.g && line_ok) ? a.g[2 * myline + 0] : 0.0;
-                    const double gb = (a.g && line_ok) ? a.g[2 * myline + 1] : 0.0;
-                    if (P.op == 1) {
-                        Ap = ga;
-                    } else if (P.op == 0) {
-                        Bp = gb;
-                    } else {
-                        // 0.5 I_L(a) + A + B mu = ga ; 0.5 I_R(b) + A mu + B = gb
-                        const double r0 = ga - 0.5 * IL0, r1 = gb - 0.5 * IRn;
-                        const double det = 1.0 - P.mu * P.mu;
-                        Ap = 2.0 * (r0 - P.mu * r1) / det;
-                        Bp = 2.0 * (r1 - P.mu * r0) / det;
-                    }
+                if (P.op != 1) {
+#pragma unroll
+                    for (int w = 0; w < NWIN; ++w) sb = fma(P.kL[w], (double)win[w], sb);
                 }
             } else {
-                if (line_ok) {
-                    const int64_t ab = 2 * (int64_t)a.nops * a.nlines * nchunks + 2 * ((int64_t)o * a.nlines + myline);
+#pragma unroll
+                for (int t = 0; t < S; ++t) {
+                    double JR = 0.0, JL = 0.0;
+#pragma unroll
+                    for (int j = 0; j < ORDER; ++j) {
+                        JR = fma(P.wR[j], (double)win[t + j], JR);
+                        JL = fma(P.wR[ORDER - 1 - j], (double)win[t + 1 + j], JL);
+                    }
+                    if (t == 0 && seg0 == 0) j0 = JR;
+                    const int64_t i = seg0 + t;
+                    if (i < n) sf = fma(P.d, sf, keepR(t) ? JR : 0.0);  // total at the last real point
+                    sb = fma(P.dpow[t], keepL(t) ? JL : 0.0, sb);
+                }
+                if (P.op == 0) sf = 0.0;
+                if (P.op == 1) sb = 0.0;
+            }
+            aF[o] = sf;
+            aB[o] = sb;
+            jr0[o] = j0;
+        }
+
+        // 3. scan of the segment totals along the line: within a wave by shuffles ...
+        double ef[NOPS], eb[NOPS];
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            const OpArgs &P = a.ops[o];
+            double xf = aF[o], xb = aB[o];
+            double e1 = 0.0, e2 = 0.0;
+            if (P.op != 0) {
+#pragma unroll
+                for (int s = 0, kx = 1; kx < GW; ++s, kx <<= 1) {
+                    const double yf = shfl_up_d(xf, kx * SL);
+                    if (gl >= kx) xf = fma(P.dseg[s], yf, xf);
+                }
+                e1 = shfl_up_d(xf, SL);
+                if (gl == 0) e1 = 0.0;
+            }
+            if (P.op != 1) {
+#pragma unroll
+                for (int s = 0, kx = 1; kx < GW; ++s, kx <<= 1) {
+                    const double yb = shfl_down_d(xb, kx * SL);
+                    if (gl + kx < GW) xb = fma(P.dseg[s], yb, xb);
+                }
+                e2 = shfl_down_d(xb, SL);
+                if (gl == GW - 1) e2 = 0.0;
+            }
+            ef[o] = e1;
+            eb[o] = e2;
+            if (line_ok) {
+                if (part == part_last) {
+                    if (g == s_last) xf_s[o][c][part] = fma(P.dpow[t_last + 1], e1, aF[o]);
+                } else if (gl == GW - 1) {
+                    xf_s[o][c][part] = xf;
+                }
+                if (gl == 0) xb_s[o][c][part] = xb;
+                if (g == 0) j0_s[o][c] = (cstart == 0) ? jr0[o] : 0.0;
+            }
+        }
+        __syncthreads();
+
+        // ... and across the wave-parts and chunks by one thread per (operator, line), which also
+        // forms the boundary constants
+        if (tid < NOPS * TC) {
+            const int o = tid / TC, cc = tid % TC;
+            const OpArgs &P = a.ops[o];
+            const int64_t L = line0 + cc;
+            if (L < a.nlines) {
+                const int64_t cidx = ((int64_t)o * a.nlines + L) * nchunks + chunk;
+                double cf = 0.0, cb = 0.0;
+                if (MODE == MODE_APPLY) {
+                    cf = a.carry[2 * cidx + 0];
+                    cb = a.carry[2 * cidx + 1];
+                }
+                double IRn = 0.0;
+                for (int p2 = 0; p2 < NP; ++p2) {
+                    cf_s[o][cc][p2] = cf;
+                    if (p2 == part_last) {
+                        const double dlp = (chunk == nchunks - 1) ? P.dlp_last : P.dlp_full;
+                        IRn = fma(dlp, cf, xf_s[o][cc][p2]);  // I_R at the tile's last point
+                    }
+                    cf = fma(P.dpart, cf, xf_s[o][cc][p2]);
+                }
+                for (int p2 = NP - 1; p2 >= 0; --p2) {
+                    cb_s[o][cc][p2] = cb;
+                    cb = fma(P.dpart, cb, xb_s[o][cc][p2]);
+                }
+                const double IL0 = cb;  // I_L at the tile's first point
+                double Ap = 0.0, Bp = 0.0;
+                if (MODE == MODE_AGG) {
+                    a.agg[3 * cidx + 0] = IRn;
+                    a.agg[3 * cidx + 1] = IL0;
+                    a.agg[3 * cidx + 2] = j0_s[o][cc];
+                } else if (MODE == MODE_FUSED) {
+                    if (a.bc == 0) {
+                        Ap = fma(P.d, IRn, j0_s[o][cc]) * P.inv1mmu;
+                        Bp = IL0 * P.inv1mmu;
+                    } else {
+                        const double ga = a.g ? a.g[2 * L + 0] : 0.0;
+                        const double gb = a.g ? a.g[2 * L + 1] : 0.0;
+                        if (P.op == 1) {
+                            Ap = ga;
+                        } else if (P.op == 0) {
+                            Bp = gb;
+                        } else {
+                            // 0.5 I_L(a) + A + B mu = ga ; 0.5 I_R(b) + A mu + B = gb
+                            const double r0 = ga - 0.5 * IL0, r1 = gb - 0.5 * IRn;
+                            const double det = 1.0 - P.mu * P.mu;
+                            Ap = 2.0 * (r0 - P.mu * r1) / det;
+                            Bp = 2.0 * (r1 - P.mu * r0) / det;
+                        }
+                    }
+                } else {
+                    const int64_t ab = 2 * (int64_t)NOPS * a.nlines * nchunks + 2 * ((int64_t)o * a.nlines + L);
                     Ap = a.carry[ab + 0];
                     Bp = a.carry[ab + 1];
                 }
+                // boundary terms at the tile's first point and at the end of its last segment
+                ab_s[o][cc][0] = decayed(Ap, P.nu, cstart);
+                const int64_t eB = a.ncells - (cstart + C - 1);
+                ab_s[o][cc][1] = (eB >= 0) ? decayed(Bp, P.nu, eB) : 0.0;
+                ab_s[o][cc][2] = (eB >= 0) ? 0.0 : Bp;  // tiles reaching past N: per-segment powers
             }
+        }
+        __syncthreads();
+        if (MODE == MODE_AGG) return;
 
-            // 6. final values: I_R + A' d^i, I_L + B' d^{N-i}, combine, D / partial sums
-            double aterm[S], bterm[S];
-            {
-                double cur = (Ap != 0.0) ? Ap * exp(-P.nu * (double)seg0) : 0.0;
+        // 5. re-sweep from the exact carries and accumulate the result
+        double fw[MULTI ? S : 1];
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            const OpArgs &P = a.ops[o];
+            const double d = P.d;
+            const double sgn = (P.k == 0) ? P.scale : -P.scale;
+            const double cR = (P.op == 1) ? sgn : (P.op == 2 ? 0.5 * sgn : 0.0);
+            const double cL = (P.op == 0) ? sgn : (P.op == 2 ? 0.5 * sgn : 0.0);
+            if (P.op != 0) {
+                // I_R at seg0 - 1; A' d^i obeys the same recurrence, so it enters once, at seg0
+                double f = fma(pw_s[o][gl], cf_s[o][c][part], ef[o]);
+                const double a0 = ab_s[o][c][0] * pp_s[o][part] * pw_s[o][gl];
+                auto fwd = [&](auto E) {
+#pragma unroll
+                    for (int t = 0; t < S; ++t) {
+                        double JR = 0.0;
+#pragma unroll
+                        for (int j = 0; j < ORDER; ++j) JR = fma(P.wR[j], (double)win[t + j], JR);
+                        if (decltype(E)::value && !keepR(t)) JR = 0.0;
+                        f = fma(d, f, JR);
+                        if (t == 0) f += a0;
+                        const double r = f;
+                        if (MULTI)
+                            fw[MULTI ? t : 0] = r;
+                        else
+                            outv[t] = fma(cR, r, outv[t]);
+                    }
+                };
+                if (edge)
+                    fwd(BoolC<true>{});
+                else
+                    fwd(BoolC<false>{});
+            }
+            if (P.op != 1) {
+                // I_L at seg0 + S and B' d^{N-i} at the segment's last point
+                double b = fma(pw_s[o][GW - 1 - gl], cb_s[o][c][part], eb[o]);
+                // B' d^{N-i} obeys the same recurrence: it enters once, at the segment's last point
+                // at or before x_N (tsb)
+                const int tsb = (a.ncells - seg0 < S - 1) ? (int)(a.ncells - seg0) : S - 1;
+                const double b0 = (ab_s[o][c][2] == 0.0)
+                                      ? ab_s[o][c][1] * pp_s[o][NP - 1 - part] * pw_s[o][GW - 1 - gl]
+                                      : decayed(ab_s[o][c][2], P.nu, a.ncells - seg0 - tsb);
+                auto bwd = [&](auto E) {
+#pragma unroll
+                    for (int t = S - 1; t >= 0; --t) {
+                        double JL = 0.0;
+#pragma unroll
+                        for (int j = 0; j < ORDER; ++j) JL = fma(P.wR[ORDER - 1 - j], (double)win[t + 1 + j], JL);
+                        if (decltype(E)::value && !keepL(t)) JL = 0.0;
+                        b = fma(d, b, JL);
+                        if (decltype(E)::value) {
+                            if (t == tsb) b += b0;
+                        } else if (t == S - 1) {
+                            b += b0;
+                        }
+                        const double r = b;
+                        if (MULTI) {
+                            const double rr = (P.op == 2) ? 0.5 * (fw[MULTI ? t : 0] + r) : r;
+                            const double wn = (double)win[t + H] - rr;
+                            outv[t] = fma(P.scale, wn, outv[t]);
+                            fw[MULTI ? t : 0] = wn;
+                        } else {
+                            outv[t] = fma(cL, r, outv[t]);
+                        }
+                    }
+                };
+                if (edge)
+                    bwd(BoolC<true>{});
+                else
+                    bwd(BoolC<false>{});
+            } else if (MULTI) {
 #pragma unroll
                 for (int t = 0; t < S; ++t) {
-                    aterm[t] = cur;
-                    cur *= d;
-                }
-                const int64_t ts64 = a.ncells - seg0;  // t with exponent 0
-                const int ts = ts64 < (S - 1) ? (int)ts64 : (S - 1);
-                double curb = (Bp != 0.0 && ts >= 0) ? Bp * exp(-P.nu * (double)(a.ncells - seg0 - ts)) : 0.0;
-#pragma unroll
-                for (int t = S - 1; t >= 0; --t) {
-                    if (t > ts) {
-                        bterm[t] = 0.0;
-                    } else {
-                        bterm[t] = curb;
-                        curb *= d;
-                    }
+                    const double wn = (double)win[t + H] - fw[MULTI ? t : 0];
+                    outv[t] = fma(P.scale, wn, outv[t]);
+                    fw[MULTI ? t : 0] = wn;
                 }
             }
-            const bool last_it = (it == kk - 1);
+        }
+
+        if (MULTI && it + 1 < kk) {
+            // the new operand D^{it+1}[v] goes through the tile to the neighbouring segments
 #pragma unroll
             for (int t = 0; t < S; ++t) {
-                const double IRf = fma(P.dpow[t + 1], Ef, lR[t]) + aterm[t];
-                const double ILf = fma(P.dpow[S - t], Eb, lL[t]) + bterm[t];
-                const double r = (P.op == 1) ? IRf : (P.op == 0) ? ILf : 0.5 * (IRf + ILf);
-                if (P.k == 0) {
-                    outv[t] = fma(P.scale, r, outv[t]);
-                } else {
-                    const double wn = (double)win[t + H] - r;
-                    outv[t] = fma(P.scale, wn, outv[t]);
-                    if (!last_it) win[t + H] = (T)wn;  // next power's operand (fused, periodic)
+                const int q = H + g * S + t;
+                tile[c * LS + q + q / S] = (T)fw[MULTI ? t : 0];
+            }
+            __syncthreads();
+            for (int e = tid; e < TC * W; e += NT) {
+                const int cc = e / W;
+                const int q = e % W;
+                const int64_t p = (int64_t)q - H;
+                if (p < 0 || p >= n) {
+                    int64_t pw = p % n;
+                    if (pw < 0) pw += n;
+                    const int qs = (int)pw + H;
+                    tile[cc * LS + q + q / S] = tile[cc * LS + qs + qs / S];
                 }
             }
-            if (!last_it) {
-                // share the new operand with neighbouring segments through the tile
-                __syncthreads();
+            __syncthreads();
 #pragma unroll
-                for (int t = 0; t < S; ++t) tile[c * LS + H + g * S + t] = win[t + H];
-                __syncthreads();
-                // periodic wrap of the halo and of the padding past the line end
-                for (int e = tid; e < TC * W; e += NT) {
-                    const int cc = e / W;
-                    const int q = e % W;
-                    const int64_t p = (int64_t)q - H;
-                    if (p < 0 || p >= n) {
-                        int64_t pw = p % n;
-                        if (pw < 0) pw += n;
-                        tile[cc * LS + q] = tile[cc * LS + H + pw];
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int w = 0; w < S + 2 * H; ++w) win[w] = tile[c * LS + g * S + w];
-            }
+            for (int w = 0; w < NWIN; ++w) win[w] = tile[wbase + w + w / S];
         }
     }
 
-    if (MODE == MODE_AGG) return;
-
-    // store through the tile so that global writes are coalesced
-    if (a.acc_mode == 1) {
-#pragma unroll
-        for (int t = 0; t < S; ++t) outv[t] += (double)win[t + H];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < S; ++t) tile[c * LS + H + g * S + t] = (T)outv[t];
-    __syncthreads();
+    // store
     T *__restrict__ out = (T *)a.out;
     const T *acc = (const T *)a.acc;
-    for (int e = tid; e < TC * C; e += NT) {
-        const int cc = CONTIG ? e / C : e % TC;
-        const int q = CONTIG ? e % C : e / TC;
-        const int64_t p = cstart + q;
-        if (line0 + cc < a.nlines && p < n) {
-            const int64_t idx = lbase[cc] + p * a.stride;
-            T val = tile[cc * LS + H + q];
-            if (a.acc_mode == 2) val += acc[idx];
-            out[idx] = val;
+    if (CONTIG) {
+        // stage through the tile so that the global writes are coalesced
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int q = H + g * S + t;
+            tile[c * LS + q + q / S] = (T)outv[t];
+        }
+        __syncthreads();
+        constexpr int STO = (TC * C + NT - 1) / NT;
+        const int nl = (int)n_loc;
+        if (TC == 1) {
+            if (line0 < a.nlines) {
+                T *op = out + lbase[0] + cstart + tid;
+                const T *ap = acc + lbase[0] + cstart + tid;
+#pragma unroll
+                for (int k = 0; k < STO; ++k) {
+                    const int q = tid + k * NT;
+                    if (q < nl) {
+                        T val = tile[(q + H) + (q + H) / S];
+                        if (a.acc_mode == 2) val += ap[k * NT];
+                        op[k * NT] = val;
+                    }
+                }
+            }
+        } else
+#pragma unroll
+        for (int k = 0; k < STO; ++k) {
+            const int e = tid + k * NT;
+            const int cc = e / C;
+            const int q = e % C;
+            if (e < TC * C && line0 + cc < a.nlines && q < nl) {
+                const int64_t idx = lbase[cc] + cstart + q;
+                T val = tile[cc * LS + (q + H) + (q + H) / S];
+                if (a.acc_mode == 2) val += acc[idx];
+                out[idx] = val;
+            }
+        }
+    } else {
+        if (line_ok) {
+            const int64_t st = a.stride;
+            int64_t idx = lbase[c] + seg0 * st;
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                if (seg0 + t < n) {
+                    double val = outv[t];
+                    if (a.acc_mode == 2) val += (double)acc[idx];
+                    out[idx] = (T)val;
+                }
+                idx += st;
+            }
         }
     }
 }
@@ -484,34 +662,24 @@ __global__ void __launch_bounds__(256) local_quad_kernel(const PassArgs a, T *JL
     const T *v = (const T *)a.v;
     const OpArgs &P = a.ops[0];
     double sr = 0.0, sl = 0.0;
-    auto at = [&](int64_t p) -> double {
-        if (a.bc == 0) {
-            p %= n;
-            if (p < 0) p += n;
-            return (double)v[base + p * s];
-        }
-        return (p >= 0 && p < n) ? (double)v[base + p * s] : 0.0;
-    };
 #pragma unroll
     for (int j = 0; j < ORDER; ++j) {
-        sr += P.wR[j] * at(i - H + j);
-        sl += P.wR[ORDER - 1 - j] * at(i - H + 1 + j);
+        sr = fma(P.wR[j], (double)line_value<T, ORDER>(a, v, base, i - H + j), sr);
+        sl = fma(P.wR[ORDER - 1 - j], (double)line_value<T, ORDER>(a, v, base, i - H + 1 + j), sl);
     }
-    if (a.bc == 1) {
-        sr = dirichlet_JR<T, ORDER>(P, v, base, s, n, i, sr);
-        sl = dirichlet_JL<T, ORDER>(P, v, base, s, n, i, sl);
-    }
+    if (a.bc == 1 && i == 0) sr = 0.0;
+    if (a.bc == 1 && i == n - 1) sl = 0.0;
     JR[gid] = (T)sr;
     JL[gid] = (T)sl;
 }
 
-// Raw sweeps: one workgroup per line, each thread a contiguous segment, scan of segment totals
-// through LDS (Hillis-Steele) -- the stand-alone debugging stage, not the fused hot path.
+// Raw sweeps: one workgroup per line, each thread a contiguous segment, serial carries between
+// the segments -- the stand-alone debugging stage, not the fused hot path.
 template <typename T>
 __global__ void __launch_bounds__(256) sweep_kernel(const PassArgs a, const T *JL, const T *JR,
                                                     T *IL, T *IR, double *ends)
 {
-    __shared__ double sf[256], sb[256], dp[256];
+    __shared__ double sf[256], sb[256], dp[256], cinf[256], cinb[256];
     const int64_t L = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t n = a.n, s = a.stride;
@@ -520,7 +688,8 @@ __global__ void __launch_bounds__(256) sweep_kernel(const PassArgs a, const T *J
     const double d = P.d;
     const int64_t seg = (n + 255) / 256;
     const int64_t i0 = tid * seg, i1 = (i0 + seg < n) ? i0 + seg : n;
-    // local sweeps (J_R[0] excluded from the forward sweep)
+    // local sweeps (J_R[0] excluded from the forward sweep; J_L of the last point excluded for
+    // Dirichlet lines)
     double f = 0.0;
     for (int64_t i = i0; i < i1; ++i) f = fma(d, f, i == 0 ? 0.0 : (double)JR[base + i * s]);
     double b = 0.0;
@@ -531,13 +700,11 @@ __global__ void __launch_bounds__(256) sweep_kernel(const PassArgs a, const T *J
     sb[tid] = b;
     dp[tid] = exp(-P.nu * (double)len);  // decay across this segment
     __syncthreads();
-    // simple serial carry by thread 0 (the stand-alone stage is not performance critical)
-    __shared__ double cinf[256], cinb[256];
     if (tid == 0) {
-        double c = 0.0;
+        double cc = 0.0;
         for (int t = 0; t < 256; ++t) {
-            cinf[t] = c;
-            c = fma(dp[t], c, sf[t]);
+            cinf[t] = cc;
+            cc = fma(dp[t], cc, sf[t]);
         }
         double cb2 = 0.0;
         for (int t = 255; t >= 0; --t) {
@@ -571,79 +738,74 @@ __global__ void __launch_bounds__(256) axpy_kernel(int64_t nel, double s, const 
     if (i < nel) y[i] = init ? (T)(s * (double)x[i]) : (T)fma(s, (double)x[i], (double)y[i]);
 }
 
-}  // namespace scx
-
 // ------------------------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------------------------
-#include "sc_launch.h"
+static const Variant kVariants[] = {
+    {16, 16, true, 256},    // 0: contiguous, lines <= 256
+    {16, 4, true, 256},     // 1: contiguous, lines <= 1024
+    {16, 1, true, 256},     // 2: contiguous, lines <= 4096
+    {16, 1, true, 512},     // 3: contiguous, lines <= 8192 (chunked beyond)
+    {16, 16, false, 256},   // 4: strided, 16 lines x 256
+    {16, 16, false, 512},   // 5: strided, 16 lines x 512
+    {16, 16, false, 1024},  // 6: strided, 16 lines x 1024 (chunked beyond 4096)
+    {16, 4, false, 1024},   // 7: strided, 4 lines x 4096
+    {8, 16, false, 1024},   // 8: strided, 16 lines x 512, short segments
+    {8, 1, true, 512},      // 9: contiguous, lines <= 4096, short segments
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-namespace scx {
+int num_variants() { return kNumVariants; }
+const Variant &variant(int id) { return kVariants[id]; }
 
-template <int ORDER, int S, int TC, bool CONTIG, int NT>
-static hipError_t launch_variant(const PassArgs &a, int mode, hipStream_t st, const char **name)
+template <int ORDER, int S, int TC, bool CONTIG, int NT, int NOPS>
+static hipError_t launch_v2(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
-    constexpr int C = (NT / TC) * S;
     const int64_t tiles = (a.nlines + TC - 1) / TC;
     if (mode == MODE_FUSED) {
-        *name = CONTIG ? "line_pass_fused_x" : "line_pass_fused_yz";
-        hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_FUSED, NT>), dim3(tiles), dim3(NT), 0, st, a);
+        if (NOPS == 1 && multi)
+            hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_FUSED, NT, 1, true>), dim3(tiles), dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_FUSED, NT, NOPS, false>), dim3(tiles), dim3(NT), 0, st, a);
         return hipGetLastError();
     }
     const dim3 grid(tiles * a.nchunks);
-    if (mode == MODE_AGG) {
-        *name = CONTIG ? "line_pass_agg_x" : "line_pass_agg_yz";
-        hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_AGG, NT>), grid, dim3(NT), 0, st, a);
-        return hipGetLastError();
-    }
-    *name = CONTIG ? "line_pass_apply_x" : "line_pass_apply_yz";
-    hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_APPLY, NT>), grid, dim3(NT), 0, st, a);
-    (void)C;
+    if (mode == MODE_AGG)
+        hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_AGG, NT, NOPS, false>), grid, dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((line_pass<double, ORDER, S, TC, CONTIG, MODE_APPLY, NT, NOPS, false>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-// Variant table: returns the chunk length of the variant chosen for this pass.
-int64_t pick_chunk(bool contig, int64_t n, int *variant)
+template <int ORDER, int S, int TC, bool CONTIG, int NT>
+static hipError_t launch_v(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
-    if (contig) {
-        if (n <= 128) { *variant = 0; return 128; }   // TC 16, NT 256, S 8
-        if (n <= 512) { *variant = 1; return 512; }   // TC 4,  NT 256, S 8
-        *variant = 2; return 4096;                    // TC 1,  NT 512, S 8
-    }
-    if (n <= 128) { *variant = 3; return 128; }        // TC 16, NT 256, S 8
-    if (n <= 256) { *variant = 4; return 256; }        // TC 16, NT 512, S 8
-    *variant = 5; return 512;                          // TC 16, NT 1024, S 8
-}
-
-int variant_S(int) { return 8; }
-int variant_GW(int variant)
-{
-    switch (variant) {
-    case 0: return 16;
-    case 1: return 64;
-    case 2: return 64;
-    default: return 4;  // strided, TC 16: 64 / 16 segments of a line per wave
-    }
+    if (a.nops == 2) return launch_v2<ORDER, S, TC, CONTIG, NT, 2>(a, mode, false, st);
+    return launch_v2<ORDER, S, TC, CONTIG, NT, 1>(a, mode, multi, st);
 }
 
 template <int ORDER>
-static hipError_t launch_order(const PassArgs &a, int variant, int mode, hipStream_t st, const char **name)
+static hipError_t launch_order(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st)
 {
-    switch (variant) {
-    case 0: return launch_variant<ORDER, 8, 16, true, 256>(a, mode, st, name);
-    case 1: return launch_variant<ORDER, 8, 4, true, 256>(a, mode, st, name);
-    case 2: return launch_variant<ORDER, 8, 1, true, 512>(a, mode, st, name);
-    case 3: return launch_variant<ORDER, 8, 16, false, 256>(a, mode, st, name);
-    case 4: return launch_variant<ORDER, 8, 16, false, 512>(a, mode, st, name);
-    case 5: return launch_variant<ORDER, 8, 16, false, 1024>(a, mode, st, name);
+    switch (vid) {
+    case 0: return launch_v<ORDER, 16, 16, true, 256>(a, mode, multi, st);
+    case 1: return launch_v<ORDER, 16, 4, true, 256>(a, mode, multi, st);
+    case 2: return launch_v<ORDER, 16, 1, true, 256>(a, mode, multi, st);
+    case 3: return launch_v<ORDER, 16, 1, true, 512>(a, mode, multi, st);
+    case 4: return launch_v<ORDER, 16, 16, false, 256>(a, mode, multi, st);
+    case 5: return launch_v<ORDER, 16, 16, false, 512>(a, mode, multi, st);
+    case 6: return launch_v<ORDER, 16, 16, false, 1024>(a, mode, multi, st);
+    case 7: return launch_v<ORDER, 16, 4, false, 1024>(a, mode, multi, st);
+    case 8: return launch_v<ORDER, 8, 16, false, 1024>(a, mode, multi, st);
+    case 9: return launch_v<ORDER, 8, 1, true, 512>(a, mode, multi, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_line_pass(const PassArgs &a, int order, int variant, int mode, hipStream_t st, const char **name)
+hipError_t launch_line_pass(const PassArgs &a, int order, int vid, int mode, bool multi, hipStream_t st)
 {
-    if (order == 4) return launch_order<4>(a, variant, mode, st, name);
-    return launch_order<6>(a, variant, mode, st, name);
+    if (order == 4) return launch_order<4>(a, vid, mode, multi, st);
+    return launch_order<6>(a, vid, mode, multi, st);
 }
 
 hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st)

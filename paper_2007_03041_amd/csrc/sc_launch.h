@@ -9,13 +9,10 @@ namespace scx {
 
 enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2 };
 
-// Kernel variant for a pass: returns the chunk length C (points of one line per workgroup).
-int64_t pick_chunk(bool contig, int64_t n, int *variant);
-int variant_S(int variant);
-int variant_GW(int variant);
+int num_variants();
+const Variant &variant(int id);
 
-hipError_t launch_line_pass(const PassArgs &a, int order, int variant, int mode, hipStream_t st,
-                            const char **name);
+hipError_t launch_line_pass(const PassArgs &a, int order, int vid, int mode, bool multi, hipStream_t st);
 hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st);
 hipError_t launch_local_quad(const PassArgs &a, int order, void *JL, void *JR, hipStream_t st);
 hipError_t launch_sweep(const PassArgs &a, const void *JL, const void *JR, void *IL, void *IR,
