@@ -263,8 +263,13 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
     const int s_last = (int)((n_loc - 1) / S);       // segment holding the tile's last real point
     const int t_last = (int)(n_loc - 1 - (int64_t)s_last * S);
     const int part_last = s_last / GW;
-    // segments holding x_0 (J_R excluded), the last point (Dirichlet: J_L excluded) or padding
-    const bool edge = (seg0 == 0) || (seg0 + S >= n);
+    // The general per-point rules (below) are needed only by waves holding padding past the line
+    // end; elsewhere the two end rules are single corrections of a linear sweep: J_R(x_0) is
+    // removed at t = 0 of the first segment, and on Dirichlet lines J_L(x_{n-1}) at t = S-1 of
+    // the segment ending at x_{n-1}.  The choice is uniform per wave, so no wave runs both paths.
+    const bool edge = __any(seg0 + S > n);
+    const bool first_seg = (seg0 == 0);
+    const bool dir_last = (a.bc == 1) && (seg0 + S == n);
     const int wbase = c * LS + g * (S + 1);
 
     T win[NWIN];
@@ -299,10 +304,28 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
                 if (P.op != 0) {
 #pragma unroll
                     for (int w = 0; w < NWIN; ++w) sf = fma(P.kR[w], (double)win[w], sf);
+                    // J_R at the segment's first point; excluded at x_0
+                    double J0 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < ORDER; ++j) J0 = fma(P.wR[j], (double)win[j], J0);
+                    if (first_seg) {
+                        sf = fma(-P.dpow[S - 1], J0, sf);
+                        j0 = J0;
+                    }
+                } else if (first_seg) {
+#pragma unroll
+                    for (int j = 0; j < ORDER; ++j) j0 = fma(P.wR[j], (double)win[j], j0);
                 }
                 if (P.op != 1) {
 #pragma unroll
                     for (int w = 0; w < NWIN; ++w) sb = fma(P.kL[w], (double)win[w], sb);
+                    if (a.bc == 1) {
+                        // J_L at the segment's last point; excluded at x_{n-1} on Dirichlet lines
+                        double JN = 0.0;
+#pragma unroll
+                        for (int j = 0; j < ORDER; ++j) JN = fma(P.wR[ORDER - 1 - j], (double)win[S + j], JN);
+                        if (dir_last) sb = fma(-P.dpow[S - 1], JN, sb);
+                    }
                 }
             } else {
 #pragma unroll
@@ -450,7 +473,11 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
                         double JR = 0.0;
 #pragma unroll
                         for (int j = 0; j < ORDER; ++j) JR = fma(P.wR[j], (double)win[t + j], JR);
-                        if (decltype(E)::value && !keepR(t)) JR = 0.0;
+                        if (decltype(E)::value) {
+                            if (!keepR(t)) JR = 0.0;
+                        } else if (t == 0 && first_seg) {
+                            JR = 0.0;
+                        }
                         f = fma(d, f, JR);
                         if (t == 0) f += a0;
                         const double r = f;
@@ -480,7 +507,11 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
                         double JL = 0.0;
 #pragma unroll
                         for (int j = 0; j < ORDER; ++j) JL = fma(P.wR[ORDER - 1 - j], (double)win[t + 1 + j], JL);
-                        if (decltype(E)::value && !keepL(t)) JL = 0.0;
+                        if (decltype(E)::value) {
+                            if (!keepL(t)) JL = 0.0;
+                        } else if (t == S - 1 && dir_last) {
+                            JL = 0.0;
+                        }
                         b = fma(d, b, JL);
                         if (decltype(E)::value) {
                             if (t == tsb) b += b0;
@@ -537,11 +568,11 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
         }
     }
 
-    // store
+    // store: along x staged through the tile so that the global writes are coalesced; along y/z
+    // the lanes of a wave already write full row segments of TC adjacent lines
     T *__restrict__ out = (T *)a.out;
     const T *acc = (const T *)a.acc;
     if (CONTIG) {
-        // stage through the tile so that the global writes are coalesced
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -565,31 +596,29 @@ __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
                     }
                 }
             }
-        } else
+        } else {
 #pragma unroll
-        for (int k = 0; k < STO; ++k) {
-            const int e = tid + k * NT;
-            const int cc = e / C;
-            const int q = e % C;
-            if (e < TC * C && line0 + cc < a.nlines && q < nl) {
-                const int64_t idx = lbase[cc] + cstart + q;
-                T val = tile[cc * LS + (q + H) + (q + H) / S];
-                if (a.acc_mode == 2) val += acc[idx];
-                out[idx] = val;
+            for (int k = 0; k < STO; ++k) {
+                const int e = tid + k * NT;
+                const int cc = e / C;
+                const int q = e % C;
+                if (e < TC * C && line0 + cc < a.nlines && q < nl) {
+                    const int64_t idx = lbase[cc] + cstart + q;
+                    T val = tile[cc * LS + (q + H) + (q + H) / S];
+                    if (a.acc_mode == 2) val += acc[idx];
+                    out[idx] = val;
+                }
             }
         }
-    } else {
-        if (line_ok) {
-            const int64_t st = a.stride;
-            int64_t idx = lbase[c] + seg0 * st;
+    } else if (line_ok) {
+        const int64_t st = a.stride;
+        const int64_t i0 = lbase[c] + seg0 * st;
 #pragma unroll
-            for (int t = 0; t < S; ++t) {
-                if (seg0 + t < n) {
-                    double val = outv[t];
-                    if (a.acc_mode == 2) val += (double)acc[idx];
-                    out[idx] = (T)val;
-                }
-                idx += st;
+        for (int t = 0; t < S; ++t) {
+            if (seg0 + t < n) {
+                double val = outv[t];
+                if (a.acc_mode == 2) val += (double)acc[i0 + t * st];
+                out[i0 + t * st] = (T)val;
             }
         }
     }
