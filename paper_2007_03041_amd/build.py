@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsc.so")
-SOURCES = ["sc_api.cpp", "sc_coeffs.cpp", "sc_kernels.hip"]
+SOURCES = ["sc_api.cpp", "sc_coeffs.cpp", "sc_kernels.hip", "sc_lp_f64_o4.hip", "sc_lp_f64_o6.hip",
+           "sc_lp_f32_o4.hip", "sc_lp_f32_o6.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -26,17 +27,29 @@ COMMON = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every unit (in parallel, one hipcc per unit) and link ``libsc.so``."""
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    running, failed = [], []
+    pending = list(cmds)
+    while pending or running:
+        while pending and len(running) < jobs:
+            cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((cmd, subprocess.Popen(cmd)))
+        cmd, proc = running.pop(0)
+        if proc.wait() != 0:
+            failed.append(cmd[-3])
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -81,7 +81,6 @@ sc_status check_grid(const sc_grid *g)
     if (!g) return fail(SC_ERR_ARG, "grid is NULL");
     if (g->ndim < 1 || g->ndim > 3) return fail(SC_ERR_ARG, "ndim must be 1, 2 or 3");
     if (g->dtype != SC_F64 && g->dtype != SC_F32_MIXED) return fail(SC_ERR_ARG, "unknown dtype");
-    if (g->dtype != SC_F64) return fail(SC_ERR_UNSUPPORTED, "only SC_F64 is implemented in this build");
     int64_t total = 1;
     for (int e = 0; e < g->ndim; ++e) {
         if (g->n[e] < 1) return fail(SC_ERR_SHAPE, "n must be >= 1 on every axis");
@@ -120,20 +119,27 @@ bool overlap(const void *a, const void *b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
-// Kernel variant for a line pass along an axis of n points (contiguous or strided).  The choice
-// can be overridden for tuning with SC_VARIANT_CONTIG / SC_VARIANT_STRIDED (variant ids).
-int pick_variant(bool contig, int64_t n)
+// Kernel variant for a line pass along an axis of n points (contiguous or strided) with elements
+// of `elem` bytes.  The choice can be overridden for tuning with SC_VARIANT_CONTIG /
+// SC_VARIANT_STRIDED (variant ids).
+int pick_variant(bool contig, int64_t n, int elem)
 {
     const char *env = std::getenv(contig ? "SC_VARIANT_CONTIG" : "SC_VARIANT_STRIDED");
     if (env && *env) {
         const int id = std::atoi(env);
-        if (id >= 0 && id < scx::num_variants() && scx::variant(id).contig == contig) return id;
+        if (scx::variant_built(id, elem) && scx::variant(id).contig == contig) return id;
     }
     if (contig) {
-        if (n <= 256) return 0;
-        if (n <= 1024) return 1;
-        if (n <= 4096) return 2;
-        return 3;
+        if (n <= 256) return 0;   // 16 lines x 256
+        if (n <= 512) return 10;  // 8 lines x 512
+        if (n <= 1024) return 1;  // 4 lines x 1024
+        if (n <= 4096) return 2;  // 1 line x 4096
+        return 3;                 // 1 line x 8192; longer lines chunked
+    }
+    if (elem == 4) {
+        // 32 adjacent float lines = 128-byte row segments
+        if (n <= 256) return 11;
+        return 12;  // 32 lines x 512; longer lines chunked
     }
     if (n <= 256) return 4;
     if (n <= 512) return 5;
@@ -177,9 +183,21 @@ void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, in
     const int64_t C = V.C();
     const int64_t nch = (ax.n + C - 1) / C;
     P->d = std::exp(-nu);
+    P->df = (float)P->d;
+    P->dlo = (float)(P->d - (double)P->df);
     P->nu = nu;
     for (int t = 0; t <= scx::MAXS; ++t) P->dpow[t] = std::exp(-nu * t);
     for (int j = 0; j < 12; ++j) P->dseg[j] = std::exp(-nu * (double)S * (double)(1 << j));
+    for (int j = 0; j < order; ++j) P->wRf[j] = (float)P->wR[j];
+    for (int w = 0; w < scx::MAXWIN; ++w) {
+        P->kRf[w] = (float)P->kR[w];
+        P->kLf[w] = (float)P->kL[w];
+    }
+    for (int t = 0; t <= scx::MAXS; ++t) P->dpowf[t] = (float)P->dpow[t];
+    for (int j = 0; j < 12; ++j) {
+        P->dseg_hi[j] = (float)P->dseg[j];
+        P->dseg_lo[j] = (float)(P->dseg[j] - (double)P->dseg_hi[j]);
+    }
     P->dpart = std::exp(-nu * (double)S * (double)V.GW());
     P->dchunk = std::exp(-nu * (double)C);
     P->dlp_full = last_part_decay(nu, std::min<int64_t>(ax.n, C), V);
@@ -219,9 +237,9 @@ size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops)
            round256(sizeof(double) * (size_t)(2 * ent + 2 * (int64_t)nops * nlines));
 }
 
-int64_t nchunks_for(const Axis &ax)
+int64_t nchunks_for(const Axis &ax, int elem)
 {
-    const int64_t C = scx::variant(pick_variant(ax.stride == 1, ax.n)).C();
+    const int64_t C = scx::variant(pick_variant(ax.stride == 1, ax.n, elem)).C();
     return (ax.n + C - 1) / C;
 }
 
@@ -231,7 +249,8 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
                    hipStream_t st)
 {
     const Axis ax = axis_of(g, dim);
-    const int vid = pick_variant(ax.stride == 1, ax.n);
+    const int elem = (int)elem_bytes(g);
+    const int vid = pick_variant(ax.stride == 1, ax.n, elem);
     const int64_t C = scx::variant(vid).C();
     scx::PassArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -261,7 +280,7 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     hipError_t e;
     if (a.nchunks == 1) {
         e = timed(contig ? "line_pass_fused_x" : "line_pass_fused_yz", st, [&](const char **) {
-            return scx::launch_line_pass(a, order, vid, scx::LMODE_FUSED, multi, st);
+            return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         return SC_OK;
@@ -272,13 +291,13 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     a.agg = (double *)wsp;
     a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
     e = timed(contig ? "line_pass_agg_x" : "line_pass_agg_yz", st, [&](const char **) {
-        return scx::launch_line_pass(a, order, vid, scx::LMODE_AGG, false, st);
+        return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_AGG, false, st);
     });
     if (e == hipSuccess)
         e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, C, st); });
     if (e == hipSuccess)
         e = timed(contig ? "line_pass_apply_x" : "line_pass_apply_yz", st, [&](const char **) {
-            return scx::launch_line_pass(a, order, vid, scx::LMODE_APPLY, false, st);
+            return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_APPLY, false, st);
         });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return SC_OK;
@@ -341,7 +360,7 @@ sc_status sc_local_quad(const sc_grid *grid, int dim, int order, double alpha, c
     fill_ext(&a, order);
     fill_op(&a.ops[0], SC_OP_0, order, alpha, ax, 0, 1.0, 0);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = timed("local_quad", st, [&](const char **) { return scx::launch_local_quad(a, order, JL, JR, st); });
+    hipError_t e = timed("local_quad", st, [&](const char **) { return scx::launch_local_quad(a, (int)elem_bytes(grid), order, JL, JR, st); });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return SC_OK;
 }
@@ -368,7 +387,7 @@ sc_status sc_sweep_LR(const sc_grid *grid, int dim, double alpha, const void *JL
     a.ops[0].d = std::exp(-alpha * ax.dx);
     a.ops[0].nu = alpha * ax.dx;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = timed("sweep", st, [&](const char **) { return scx::launch_sweep(a, JL, JR, IL, IR, line_ends, st); });
+    hipError_t e = timed("sweep", st, [&](const char **) { return scx::launch_sweep(a, (int)elem_bytes(grid), JL, JR, IL, IR, line_ends, st); });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return SC_OK;
 }
@@ -381,13 +400,13 @@ size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k)
         size_t extra = 0;
         for (int d = 0; d < grid->ndim; ++d) {
             const Axis ax = axis_of(grid, d);
-            extra = std::max(extra, chunk_ws_bytes(ax.nlines, nchunks_for(ax), 2));
+            extra = std::max(extra, chunk_ws_bytes(ax.nlines, nchunks_for(ax, (int)elem_bytes(grid)), 2));
         }
         return b + extra + 256;
     }
     if (dim < 0 || dim >= grid->ndim) return 0;
     const Axis ax = axis_of(grid, dim);
-    const int64_t nch = nchunks_for(ax);
+    const int64_t nch = nchunks_for(ax, (int)elem_bytes(grid));
     size_t b = chunk_ws_bytes(ax.nlines, nch, 1);
     if (which == 1 && nch > 1 && k > 1) b += 2 * round256((size_t)ax.total * elem_bytes(grid));
     return b + 256;
@@ -425,7 +444,7 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int ord
     if (overlap(v, out, bytes)) return fail(SC_ERR_ARG, "out overlaps v");
     if (ws && ((uintptr_t)ws & 255)) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
-    if (nchunks_for(ax) == 1 || k == 1) {
+    if (nchunks_for(ax, (int)elem_bytes(grid)) == 1 || k == 1) {
         OpSpec o{(int)op, alpha, scale, k};
         return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes, st);
     }
@@ -443,7 +462,7 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int ord
         s = run_pass(grid, dim, order, &o, 1, prev, nullptr, 0, dst, dirichlet_g, rest, rest_bytes, st);
         if (s != SC_OK) return s;
         hipError_t e = timed("axpy", st, [&](const char **) {
-            return scx::launch_axpy(ax.total, scale, dst, out, p == 1 ? 1 : 0, st);
+            return scx::launch_axpy(ax.total, (int)elem_bytes(grid), scale, dst, out, p == 1 ? 1 : 0, st);
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         prev = dst;

@@ -31,6 +31,16 @@ struct OpArgs {
     double scale;           // result multiplier
     int32_t op;             // 0 = L_L^{-1}, 1 = L_R^{-1}, 2 = L_0^{-1}
     int32_t k;              // 0: result is L^{-1}[v]; k >= 1: result is sum_{p=1..k} D^p[v]
+    // FP32 passes: the per-point coefficients rounded once from the FP64 values above, and the
+    // in-wave scan decays split as hi + lo (hi = fl32(d^{S 2^j}), lo = fl32(d^{S 2^j} - hi))
+    float wRf[6];
+    float kRf[MAXWIN];
+    float kLf[MAXWIN];
+    float df;
+    float dlo;              // d - fl32(d): the FP32 sweeps apply d as df + dlo
+    float dpowf[MAXS + 1];
+    float dseg_hi[12];
+    float dseg_lo[12];
 };
 
 struct PassArgs {
@@ -65,9 +75,39 @@ struct Variant {
     int TC;      // lines per tile
     bool contig; // lanes along the line (contiguous axis) or across lines (strided axis)
     int NT;      // threads per workgroup
-    int G() const { return NT / TC; }
-    int C() const { return G() * S; }
-    int GW() const { return contig ? (G() < WAVE ? G() : WAVE) : WAVE / TC; }
+    constexpr int G() const { return NT / TC; }
+    constexpr int C() const { return G() * S; }
+    constexpr int GW() const { return contig ? (G() < WAVE ? G() : WAVE) : WAVE / TC; }
+    constexpr int NP() const { return G() / GW(); }
+    // static LDS of the line pass with this shape: the tile (padded, odd line stride), line bases,
+    // four carry tables, J_R(x_0), boundary terms and two decay tables
+    constexpr int lds_bytes(int elem, int order, int nops) const
+    {
+        const int W = C() + order;
+        const int LS = (W + W / S + 1) | 1;
+        return TC * LS * elem + TC * 8 + 4 * nops * TC * NP() * 8 + nops * TC * 8 + nops * TC * 3 * 8 +
+               nops * (GW() + 1) * 8 + nops * (NP() + 1) * 8;
+    }
 };
+
+constexpr int LDS_LIMIT = 160 * 1024;  // LDS per workgroup on gfx950
+
+// The kernel variants: X(id, S, TC, CONTIG, NT).  A variant is built for an element type only where
+// its LDS fits (Variant::lds_bytes with two operators).
+#define SC_VARIANTS(X)             \
+    X(0, 16, 16, true, 256)        \
+    X(1, 16, 4, true, 256)         \
+    X(2, 16, 1, true, 256)         \
+    X(3, 16, 1, true, 512)         \
+    X(4, 16, 16, false, 256)       \
+    X(5, 16, 16, false, 512)       \
+    X(6, 16, 16, false, 1024)      \
+    X(7, 16, 4, false, 1024)       \
+    X(8, 8, 16, false, 1024)       \
+    X(9, 8, 1, true, 512)          \
+    X(10, 16, 8, true, 256)        \
+    X(11, 16, 32, false, 512)      \
+    X(12, 16, 32, false, 1024)     \
+    X(13, 8, 32, false, 1024)
 
 }  // namespace scx
