@@ -55,8 +55,10 @@ typedef enum {
 
 typedef enum {
     SC_F64 = 0,      /* FP64 data and arithmetic */
-    SC_F32_MIXED = 1 /* FP32 data, quadrature and in-segment sweeps with compensated carries;
-                        FP64 boundary constants (A,B) and cross-segment / cross-chunk carries */
+    SC_F32_MIXED = 1 /* FP32 data, quadrature and in-segment sweeps; in-wave carries as compensated
+                        FP32 (hi, lo) pairs; FP64 boundary constants (A,B) and carries across
+                        wave-parts and chunks.  sc_local_quad / sc_sweep_LR accumulate in FP64 and
+                        round their FP32 outputs once. */
 } sc_dtype;
 
 typedef enum { SC_OP_L = 0, SC_OP_R = 1, SC_OP_0 = 2 } sc_op; /* L_L^{-1}, L_R^{-1}, L_0^{-1} */
