@@ -39,7 +39,7 @@ def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2007_03041_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".inc")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
@@ -142,6 +142,55 @@ def heat3d_legs(sc, torch, reps=4):
     out["mixed_f32"]["max_rel_err_vs_f64_path"] = d / res["f64"].abs().max().item()
     out["workload"] = ("3-D heat equation, 512^3 incl. boundaries, Dirichlet 0, order-6 quadrature, 5 "
                        "dimension-split steps, dt=dx, beta=1, 16 seeded Gaussian bumps")
+    return out
+
+
+def batch_legs(sc, torch, reps=5):
+    """The batched workload (4096 independent instances on [0, 1], line lengths U{256..16384},
+    beta U(0.5, 2), periodic or Dirichlet, 1/16 of them with 256 lines; L_0^{-1} or D_0 per
+    instance), FP64 and mixed: the autotuned, graph-replayed batch against one launch per instance
+    through the single-instance entry points."""
+    from paper_2007_03041_amd import workloads as W
+
+    items, total, ms, ng = W.batch_instances(dirichlet_values=True)
+    v64, gv = W.batch_data(items, total, ms, device="cuda", ngvals=ng)
+    out = {"workload": "4096 instances, lengths U{256..16384}, beta U(0.5,2), periodic/Dirichlet, 1/16 2-D "
+                       "(256 lines), order 6, L_0^{-1} or D_0", "dof": total}
+    for name, dtype, tdt in (("f64", sc.SC_F64, torch.float64), ("mixed_f32", sc.SC_F32_MIXED, torch.float32)):
+        v = v64.to(tdt)
+        o = torch.empty_like(v)
+        plan = sc.BatchPlan(items, dtype=dtype, order=6)
+        t0 = time.perf_counter()
+        plan.tune(v, out=o, g=gv, reps=2)
+        t_tune = time.perf_counter() - t0
+        plan.apply(v, out=o, g=gv, use_graph=True)
+        ref = plan.apply_per_instance(v, g=gv)
+        torch.cuda.synchronize()
+        rel = ((o.double() - ref.double()).abs().max() / ref.double().abs().max()).item()
+        res = {}
+        for mode in ("graph", "per_instance"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                if mode == "graph":
+                    plan.apply(v, out=o, g=gv, use_graph=True)
+                else:
+                    plan.apply_per_instance(v, out=o, g=gv)
+            torch.cuda.synchronize()
+            res[mode] = (time.perf_counter() - t0) / reps
+        elem = 8 if dtype == sc.SC_F64 else 4
+        out[name] = {
+            "graph_ms": 1e3 * res["graph"],
+            "per_instance_ms": 1e3 * res["per_instance"],
+            "speedup_vs_per_instance": res["per_instance"] / res["graph"],
+            "dof_per_s": total / res["graph"],
+            "hbm_frac_algorithmic": 2 * elem * total / res["graph"] / 1e9 / HBM_PEAK_GBS,
+            "tune_s": t_tune,
+            "shapes": plan.describe()["shapes"],
+            "max_rel_diff_vs_per_instance": rel,
+        }
+        plan.close()
+        del v, o, ref
     return out
 
 
@@ -254,6 +303,8 @@ def main():
     if not args.no_extra:
         del fields, stepper
         out["beside"] = {"heat3d_512": heat3d_legs(sc, torch)}
+        torch.cuda.empty_cache()
+        out["beside"]["batch_4096"] = batch_legs(sc, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, torch, grid, pde_kw)
     print(json.dumps(out), flush=True)

@@ -136,6 +136,56 @@ double sc_effective_dt(const sc_grid *grid, const sc_linear_pde *pde);
 
 const char *sc_last_error(void);
 
+/* ------------------------------------------------------------------------------------------------
+ * Batches of independent instances.  Instance i is nlines lines of n contiguous points at element
+ * offset `offset` of the batch arrays v and out (the same offset in both; dtype of the plan), each
+ * line on [lo, hi] with the grid convention of sc_grid, its own alpha, boundary and operator.  The
+ * plan applies, along every instance's lines, L_op^{-1} (k = 0) or scale * D (k = 1) -- the
+ * operations of sc_apply_invL / sc_apply_D_partial_sum -- in one launch per tile shape.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t offset;   /* element offset of the instance's first point in v and out */
+    int64_t n;        /* points per line, >= order + 1 */
+    int64_t nlines;   /* >= 1 */
+    double lo, hi;
+    double alpha;     /* > 0, alpha dx < 700 */
+    double scale;     /* result multiplier for k = 1 */
+    int64_t g_offset; /* Dirichlet values: 2 per line (a, b) from this FP64 offset of g; -1 = zero */
+    int32_t bc;       /* sc_bc */
+    int32_t op;       /* sc_op */
+    int32_t k;        /* 0 or 1 */
+    int32_t reserved; /* 0 */
+} sc_batch_item;
+
+typedef struct sc_batch_plan_s *sc_batch_plan;
+
+/* Validates the instances (copied) and prepares the launches with the tile shapes the autotuner
+ * chose earlier in this process for instances of the same class (line length rounded up to a
+ * power of two; single- or multi-line), default shapes otherwise.  Allocates the plan's device
+ * tables (hipMalloc) on the current device and a private capture stream.  dtype: sc_dtype. */
+sc_status sc_batch_plan_create(const sc_batch_item *items, int count, int dtype, int order, sc_batch_plan *plan);
+sc_status sc_batch_plan_destroy(sc_batch_plan plan);
+/* Workspace bytes enough for any tile shape and for sc_batch_apply_per_instance. */
+size_t sc_batch_workspace_bytes(sc_batch_plan plan);
+/* Elements of v and out the instances span (max of offset + n * nlines). */
+int64_t sc_batch_elements(sc_batch_plan plan);
+/* Enqueues the batch on `stream`.  use_graph = 1: the launches are captured once into a HIP graph
+ * (re-captured when an array pointer changes) and replayed with one hipGraphLaunch.  out must not
+ * overlap v; g (FP64 device) is needed if any instance has g_offset >= 0. */
+sc_status sc_batch_apply(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws, size_t ws_bytes,
+                         int use_graph, sc_stream_t stream);
+/* The same results through one sc_apply_invL / sc_apply_D_partial_sum call per instance. */
+sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws,
+                                      size_t ws_bytes, sc_stream_t stream);
+/* Autotuner: times every candidate tile shape (persistent or one workgroup per work item) on each
+ * class of the plan's instances, `reps` runs each, on the caller's arrays (out is overwritten),
+ * keeps the fastest per class for this plan and for plans created later in the process.
+ * Synchronises `stream`; needs ws_bytes >= sc_batch_workspace_bytes(plan). */
+sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws, size_t ws_bytes,
+                        int reps, sc_stream_t stream);
+/* JSON description of the plan's launches and tile shapes; returns its length (buf may be NULL). */
+int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
+
 /* Optional per-kernel timing with HIP events recorded on the caller's stream around every launch
  * the library makes (for benchmarks).  sc_timing_read returns the number of kernel names written;
  * ms[i] is the summed elapsed time and counts[i] the launches of names[i] since the last reset.

@@ -29,7 +29,10 @@ _STATUS = {0: "SC_OK", -1: "SC_ERR_ARG", -2: "SC_ERR_SHAPE", -3: "SC_ERR_UNSUPPO
 # exported symbols of include/sc.h
 SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum",
            "sc_time_step", "sc_workspace_bytes", "sc_effective_dt", "sc_last_error",
-           "sc_timing_enable", "sc_timing_read", "sc_timing_reset")
+           "sc_timing_enable", "sc_timing_read", "sc_timing_reset",
+           "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_workspace_bytes",
+           "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
+           "sc_batch_describe")
 
 
 class ScError(RuntimeError):
@@ -47,6 +50,12 @@ class sc_linear_pde(ctypes.Structure):
     _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double), ("dt", c_double),
                 ("order", c_int32), ("nn_policy", c_int32), ("nn_eps", c_double),
                 ("block_len", c_double), ("split", c_int32), ("reserved", c_int32)]
+
+
+class sc_batch_item(ctypes.Structure):
+    _fields_ = [("offset", c_int64), ("n", c_int64), ("nlines", c_int64), ("lo", c_double), ("hi", c_double),
+                ("alpha", c_double), ("scale", c_double), ("g_offset", c_int64), ("bc", c_int32),
+                ("op", c_int32), ("k", c_int32), ("reserved", c_int32)]
 
 
 @dataclass
@@ -110,8 +119,21 @@ def load():
     lib.sc_timing_read.restype = c_int
     lib.sc_timing_reset.argtypes = []
     lib.sc_timing_reset.restype = None
+    bp = c_void_p
+    lib.sc_batch_plan_create.argtypes = [POINTER(sc_batch_item), c_int, c_int, c_int, POINTER(c_void_p)]
+    lib.sc_batch_plan_destroy.argtypes = [bp]
+    lib.sc_batch_workspace_bytes.argtypes = [bp]
+    lib.sc_batch_workspace_bytes.restype = c_size_t
+    lib.sc_batch_elements.argtypes = [bp]
+    lib.sc_batch_elements.restype = c_int64
+    lib.sc_batch_apply.argtypes = [bp, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
+    lib.sc_batch_apply_per_instance.argtypes = [bp, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.sc_batch_tune.argtypes = [bp, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
+    lib.sc_batch_describe.argtypes = [bp, c_char_p, c_int]
+    lib.sc_batch_describe.restype = c_int
     for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum", "sc_time_step",
-              "sc_timing_enable"):
+              "sc_timing_enable", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
+              "sc_batch_apply_per_instance", "sc_batch_tune"):
         getattr(lib, f).restype = c_int
     _lib = lib
     return lib
@@ -293,3 +315,85 @@ def timing_read(max_entries: int = 32):
     cnt = (c_int * max_entries)()
     m = lib.sc_timing_read(ctypes.cast(names, POINTER(c_char * 64)), ms, cnt, max_entries)
     return {bytes(names[i]).split(b"\0", 1)[0].decode(): (ms[i], cnt[i]) for i in range(m)}
+
+
+class BatchPlan:
+    """A plan over many independent instances (``sc_batch_*``).
+
+    ``items``: sequence of dicts with keys offset, n, nlines, lo, hi, alpha, bc ("periodic" or
+    "dirichlet"), op ("L", "R", "0"), k (0 or 1), and optionally scale (default 1) and g_offset
+    (default -1).  Arrays are flat contiguous device tensors of the plan's dtype (float64 for
+    SC_F64, float32 for SC_F32_MIXED) with at least ``elements`` entries.
+    """
+
+    def __init__(self, items, dtype: int = SC_F64, order: int = 6, device="cuda"):
+        lib = load()
+        arr = (sc_batch_item * len(items))()
+        for i, it in enumerate(items):
+            e = arr[i]
+            e.offset, e.n, e.nlines = int(it["offset"]), int(it["n"]), int(it["nlines"])
+            e.lo, e.hi, e.alpha = float(it["lo"]), float(it["hi"]), float(it["alpha"])
+            e.scale = float(it.get("scale", 1.0))
+            e.g_offset = int(it.get("g_offset", -1))
+            e.bc, e.op, e.k, e.reserved = BCS[it["bc"]], OPS[it["op"]], int(it["k"]), 0
+        self._h = c_void_p()
+        _check(lib.sc_batch_plan_create(arr, len(items), dtype, order, ctypes.byref(self._h)))
+        self.dtype, self.order, self.count = dtype, order, len(items)
+        self.elements = int(lib.sc_batch_elements(self._h))
+        self._ws, self._wsp = _workspace(int(lib.sc_batch_workspace_bytes(self._h)), device)
+        self._nbytes = 0 if self._ws is None else self._ws.numel() - 256
+
+    def _arrays(self, v, out, g):
+        import torch
+
+        want = torch.float64 if self.dtype == SC_F64 else torch.float32
+        for name, t in (("v", v), ("out", out)):
+            if not (t.is_cuda and t.dtype == want and t.is_contiguous() and t.numel() >= self.elements):
+                raise ValueError(f"{name}: contiguous {want} device tensor with >= {self.elements} elements")
+        if g is not None and not (g.is_cuda and g.dtype == torch.float64 and g.is_contiguous()):
+            raise ValueError("g: contiguous float64 device tensor")
+        return v.data_ptr(), out.data_ptr(), None if g is None else g.data_ptr()
+
+    def apply(self, v, out=None, g=None, use_graph: bool = False):
+        import torch
+
+        out = torch.empty_like(v) if out is None else out
+        vp, op_, gp = self._arrays(v, out, g)
+        _check(load().sc_batch_apply(self._h, vp, op_, gp, self._wsp, self._nbytes, 1 if use_graph else 0,
+                                     _stream()))
+        return out
+
+    def apply_per_instance(self, v, out=None, g=None):
+        import torch
+
+        out = torch.empty_like(v) if out is None else out
+        vp, op_, gp = self._arrays(v, out, g)
+        _check(load().sc_batch_apply_per_instance(self._h, vp, op_, gp, self._wsp, self._nbytes, _stream()))
+        return out
+
+    def tune(self, v, out=None, g=None, reps: int = 3):
+        import torch
+
+        out = torch.empty_like(v) if out is None else out
+        vp, op_, gp = self._arrays(v, out, g)
+        _check(load().sc_batch_tune(self._h, vp, op_, gp, self._wsp, self._nbytes, reps, _stream()))
+
+    def describe(self) -> dict:
+        import json
+
+        lib = load()
+        n = lib.sc_batch_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.sc_batch_describe(self._h, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().sc_batch_plan_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

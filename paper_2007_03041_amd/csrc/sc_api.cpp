@@ -17,11 +17,19 @@
 #include <vector>
 
 #include "sc_device.h"
+#include "sc_host.h"
 #include "sc_launch.h"
 
-namespace {
-
 thread_local std::string g_err;
+
+namespace scx {
+namespace host {
+
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_records;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
+size_t g_pool_used = 0;
 
 sc_status fail(sc_status s, const std::string &msg)
 {
@@ -30,51 +38,8 @@ sc_status fail(sc_status s, const std::string &msg)
 }
 
 // ------------------------------------------------------------------------------------------
-// optional per-kernel timing (events on the caller's stream)
-// ------------------------------------------------------------------------------------------
-struct TimedLaunch {
-    std::string name;
-    hipEvent_t start, stop;
-};
-std::mutex g_tmu;
-bool g_timing = false;
-std::vector<TimedLaunch> g_records;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
-size_t g_pool_used = 0;
-
-template <typename F>
-hipError_t timed(const char *fallback_name, hipStream_t st, F &&launch)
-{
-    if (!g_timing) {
-        const char *nm = fallback_name;
-        return launch(&nm);
-    }
-    std::lock_guard<std::mutex> lk(g_tmu);
-    if (g_pool_used == g_pool.size()) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
-        g_pool.emplace_back(a, b);
-    }
-    auto ev = g_pool[g_pool_used++];
-    hipError_t e = hipEventRecord(ev.first, st);
-    if (e != hipSuccess) return e;
-    const char *nm = fallback_name;
-    e = launch(&nm);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev.second, st);
-    if (e != hipSuccess) return e;
-    g_records.push_back({nm ? std::string(nm) : std::string(fallback_name), ev.first, ev.second});
-    return e;
-}
-
-// ------------------------------------------------------------------------------------------
 // grid helpers
 // ------------------------------------------------------------------------------------------
-struct Axis {
-    int64_t n, stride, nlines, ncells, total;
-    double dx, len;
-    int bc;
-};
 
 sc_status check_grid(const sc_grid *g)
 {
@@ -223,11 +188,6 @@ void fill_ext(scx::PassArgs *a, int order)
         }
 }
 
-struct OpSpec {
-    int op;
-    double alpha, scale;
-    int k;
-};
 
 size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops)
 {
@@ -329,7 +289,10 @@ double nn_bound(const sc_grid *g, const sc_linear_pde *p)
     return b;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace scx
+
+using namespace scx::host;
 
 // ------------------------------------------------------------------------------------------
 // ABI

@@ -69,6 +69,25 @@ struct PassArgs {
     OpArgs ops[2];
 };
 
+// One instance of a batched pass: its argument block (array pointers unused) and the element offsets
+// of its arrays in the batch buffers: operand and result at v_off, Dirichlet values at g_off (< 0:
+// zero), chunk aggregates and carries at agg_off / carry_off doubles into the workspace.
+struct BatchArgs {
+    PassArgs a;
+    int64_t v_off;
+    int64_t g_off;
+    int64_t agg_off;
+    int64_t carry_off;
+};
+
+// One work item of a batched launch: tile `tile` (line tile, times chunks for chunked passes) of
+// instance `item`.
+struct BatchWork {
+    int32_t item;
+    int32_t pad_;
+    int64_t tile;
+};
+
 // Tile shape of a kernel variant.
 struct Variant {
     int S;       // points per thread segment
@@ -108,6 +127,8 @@ constexpr int LDS_LIMIT = 160 * 1024;  // LDS per workgroup on gfx950
     X(10, 16, 8, true, 256)        \
     X(11, 16, 32, false, 512)      \
     X(12, 16, 32, false, 1024)     \
-    X(13, 8, 32, false, 1024)
+    X(13, 8, 32, false, 1024)      \
+    X(14, 16, 1, true, 64)         \
+    X(15, 16, 1, true, 1024)
 
 }  // namespace scx

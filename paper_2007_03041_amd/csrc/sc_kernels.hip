@@ -9,20 +9,27 @@ extern template hipError_t launch_line_pass_t<double, 4>(const PassArgs &, int, 
 extern template hipError_t launch_line_pass_t<double, 6>(const PassArgs &, int, int, bool, hipStream_t);
 extern template hipError_t launch_line_pass_t<float, 4>(const PassArgs &, int, int, bool, hipStream_t);
 extern template hipError_t launch_line_pass_t<float, 6>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<double, 4>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<double, 6>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 4>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 6>(const BatchLaunch &, int, hipStream_t);
+extern template int line_pass_batch_occupancy_t<double, 4>(int, int);
+extern template int line_pass_batch_occupancy_t<double, 6>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 4>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 6>(int, int);
 
 // Chunk carries of chunked passes: one thread per (op, line) walks the chunk totals in both
 // directions (Sec. 3, eqs. (Left-/Right-moving integral DD) with exact attenuation factors) and
 // forms the boundary constants.
-__global__ void __launch_bounds__(256) chunk_carry(const PassArgs a, int64_t chunk_len)
+__device__ void chunk_carry_one(const PassArgs &a, const double *agg, double *carry, const double *g,
+                                int64_t chunk_len, int64_t idx)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)a.nops * a.nlines) return;
     const int o = (int)(idx / a.nlines);
     const int64_t L = idx % a.nlines;
     const OpArgs &P = a.ops[o];
     const int64_t nch = a.nchunks;
-    const double *ag = a.agg + ((int64_t)o * a.nlines + L) * nch * 3;
-    double *cr = const_cast<double *>(a.carry) + ((int64_t)o * a.nlines + L) * nch * 2;
+    const double *ag = agg + ((int64_t)o * a.nlines + L) * nch * 3;
+    double *cr = carry + ((int64_t)o * a.nlines + L) * nch * 2;
     const int64_t len_last = a.n - (nch - 1) * chunk_len;
     const double d_last = exp(-P.nu * (double)len_last);
     double E = 0.0;
@@ -41,8 +48,8 @@ __global__ void __launch_bounds__(256) chunk_carry(const PassArgs a, int64_t chu
         Ap = fma(P.d, IRn, J0) * P.inv1mmu;
         Bp = IL0 * P.inv1mmu;
     } else {
-        const double ga = a.g ? a.g[2 * L + 0] : 0.0;
-        const double gb = a.g ? a.g[2 * L + 1] : 0.0;
+        const double ga = g ? g[2 * L + 0] : 0.0;
+        const double gb = g ? g[2 * L + 1] : 0.0;
         if (P.op == 1) {
             Ap = ga;
         } else if (P.op == 0) {
@@ -54,9 +61,28 @@ __global__ void __launch_bounds__(256) chunk_carry(const PassArgs a, int64_t chu
             Bp = 2.0 * (r1 - P.mu * r0) / det;
         }
     }
-    double *ab = const_cast<double *>(a.carry) + 2 * (int64_t)a.nops * a.nlines * nch + 2 * idx;
+    double *ab = carry + 2 * (int64_t)a.nops * a.nlines * nch + 2 * idx;
     ab[0] = Ap;
     ab[1] = Bp;
+}
+
+__global__ void __launch_bounds__(256) chunk_carry(const PassArgs a, int64_t chunk_len)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.nops * a.nlines) return;
+    chunk_carry_one(a, a.agg, const_cast<double *>(a.carry), a.g, chunk_len, idx);
+}
+
+// Batched chunk carries: workgroup b serves every (operator, line) of instance items[b].
+__global__ void __launch_bounds__(256) chunk_carry_batch(const BatchArgs *__restrict__ table,
+                                                         const int32_t *__restrict__ items, int64_t chunk_len,
+                                                         const double *gbase, double *wsbase)
+{
+    const BatchArgs &b = table[items[blockIdx.x]];
+    const int64_t cnt = (int64_t)b.a.nops * b.a.nlines;
+    for (int64_t idx = threadIdx.x; idx < cnt; idx += blockDim.x)
+        chunk_carry_one(b.a, wsbase + b.agg_off, wsbase + b.carry_off, b.g_off >= 0 ? gbase + b.g_off : nullptr,
+                        chunk_len, idx);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -185,6 +211,34 @@ hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int
     }
     if (order == 4) return launch_line_pass_t<float, 4>(a, vid, mode, multi, st);
     return launch_line_pass_t<float, 6>(a, vid, mode, multi, st);
+}
+
+hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st)
+{
+    if (!variant_built(vid, elem) || !variant(vid).contig) return hipErrorInvalidValue;
+    if (b.nwork <= 0) return hipSuccess;
+    if (elem == 8) {
+        if (order == 4) return launch_line_pass_batch_t<double, 4>(b, vid, st);
+        return launch_line_pass_batch_t<double, 6>(b, vid, st);
+    }
+    if (order == 4) return launch_line_pass_batch_t<float, 4>(b, vid, st);
+    return launch_line_pass_batch_t<float, 6>(b, vid, st);
+}
+
+int line_pass_batch_occupancy(int elem, int order, int vid, int mode)
+{
+    if (!variant_built(vid, elem) || !variant(vid).contig) return 0;
+    if (elem == 8) return order == 4 ? line_pass_batch_occupancy_t<double, 4>(vid, mode)
+                                     : line_pass_batch_occupancy_t<double, 6>(vid, mode);
+    return order == 4 ? line_pass_batch_occupancy_t<float, 4>(vid, mode) : line_pass_batch_occupancy_t<float, 6>(vid, mode);
+}
+
+hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems, int64_t chunk_len,
+                                    const double *g, double *ws, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(chunk_carry_batch, dim3(nitems), dim3(256), 0, st, table, items, chunk_len, g, ws);
+    return hipGetLastError();
 }
 
 hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st)

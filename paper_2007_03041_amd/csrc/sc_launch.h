@@ -22,9 +22,32 @@ hipError_t launch_sweep(const PassArgs &a, int elem, const void *JL, const void 
                         double *ends, hipStream_t st);
 hipError_t launch_axpy(int64_t nel, int elem, double s, const void *x, void *y, int init, hipStream_t st);
 
+// One launch of the persistent batched pass (x lines of many instances, one tile shape).
+struct BatchLaunch {
+    const BatchArgs *table;  // device
+    const BatchWork *work;   // device
+    int64_t nwork;
+    int64_t grid;            // workgroups (<= nwork)
+    const void *v;
+    void *out;
+    const double *g;
+    double *ws;
+    int mode;                // LMODE_*
+};
+
+hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st);
+// resident workgroups per CU of the batched pass (0 if the variant is not built for x lines)
+int line_pass_batch_occupancy(int elem, int order, int vid, int mode);
+hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems, int64_t chunk_len,
+                                    const double *g, double *ws, hipStream_t st);
+
 // one instantiation unit per (element type, order): sc_lp_<type>_o<order>.hip
 template <typename T, int ORDER>
 hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st);
+template <typename T, int ORDER>
+hipError_t launch_line_pass_batch_t(const BatchLaunch &b, int vid, hipStream_t st);
+template <typename T, int ORDER>
+int line_pass_batch_occupancy_t(int vid, int mode);
 
 double moment(int q, double nu);
 void quad_weights(double nu, int m, const int *eta, double *w);

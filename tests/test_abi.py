@@ -82,3 +82,22 @@ def test_workspace_sizes():
     assert sc.workspace_bytes(g, 0, 0) > 0          # x lines of 100: single tile
     assert sc.workspace_bytes(g, 1, 0) > 1000       # y lines of 5000: chunked aggregates
     assert sc.workspace_bytes(g, 0, 2) >= 100 * 5000 * 8
+
+
+def test_batch_validation_before_device_use():
+    """Invalid batch instances are rejected before any device call."""
+    lib = sc.load()
+    base = dict(offset=0, n=100, nlines=1, lo=0.0, hi=1.0, alpha=50.0, scale=1.0, g_offset=-1, bc=0, op=2, k=0)
+    cases = [(dict(n=6), sc.SC_ERR_SHAPE), (dict(k=2), sc.SC_ERR_UNSUPPORTED), (dict(alpha=0.0), sc.SC_ERR_ARG),
+             (dict(bc=5), sc.SC_ERR_ARG), (dict(op=3), sc.SC_ERR_ARG), (dict(g_offset=0), sc.SC_ERR_ARG),
+             (dict(nlines=0), sc.SC_ERR_SHAPE), (dict(alpha=1e6), sc.SC_ERR_ARG)]
+    for bad, want in cases:
+        arr = (sc.sc_batch_item * 1)()
+        for k, v in dict(base, **bad).items():
+            setattr(arr[0], k, v)
+        h = ctypes.c_void_p()
+        assert lib.sc_batch_plan_create(arr, 1, sc.SC_F64, 6, ctypes.byref(h)) == want, bad
+        assert not h.value
+    arr = (sc.sc_batch_item * 1)()
+    assert lib.sc_batch_plan_create(arr, 0, sc.SC_F64, 6, ctypes.byref(ctypes.c_void_p())) == sc.SC_ERR_ARG
+    assert lib.sc_batch_plan_create(arr, 1, sc.SC_F64, 5, ctypes.byref(ctypes.c_void_p())) == sc.SC_ERR_UNSUPPORTED
