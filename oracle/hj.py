@@ -1,0 +1,189 @@
+"""Oracle of the nonlinear Hamilton-Jacobi example: WENO local quadrature, Lax-Friedrichs numerical
+Hamiltonian, adaptive explicit steps.  Plain numpy, FP64.
+
+TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT (same rules as the package: only ``tests/``,
+``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg may use it).  The sweeps are the
+C oracle's (``line_sweep``); everything else is written out here in the paper's order.
+
+Readings (the paper gives the nonlinear quadrature only in outline, Sec. 2.4, and cites prior work
+for the details):
+  * 5-point quadrature from three 3-point substencils.  J_R[i] integrates the cell [x_{i-1}, x_i]
+    against nu e^{-nu eta} (eta = distance from x_i in units of dx) over the nodes x_{i-3}..x_{i+1};
+    substencil S_r = {x_{i-3+r}, x_{i-2+r}, x_{i-1+r}}, r = 0, 1, 2.  J_L is the mirror image
+    (cell [x_i, x_{i+1}], nodes x_{i+3}..x_{i-1}).
+  * Linear weights d_r: the partition of unity with sum_r d_r J^(r) = J^(5-point) (Sec. 2.4, the
+    linear-weight combination), solved here by least squares over the 5 node coefficients.
+  * Smoothness of substencil r: beta_r = sum_{l >= 2} dx^{2l-3} int_cell (p_r^(l))^2 dx over the
+    derivative orders the interpolant has (the paper's commented indicator starts at l = 2; for the
+    quadratic p_r only l = 2 remains).
+  * Nonlinear weights: WENO-Z, w~_r = d_r (1 + tau / (eps + beta_r)), tau = |beta_0 - beta_2|,
+    eps = 1e-6, normalised to sum 1.
+  * Lax-Friedrichs Hamiltonian (Sec. 2.5): H^(v-, v+) = H((v- + v+)/2) + r (v- - v+)/2 per axis,
+    r = the global max |H_p| (lagged), with v- = alpha D_R[u], v+ = -alpha D_L[u] (s = 1).
+  * Adaptive step: dt = CFL min(dx / c_x, dy / c_y) with lagged wave speeds c = max |u_x| (the
+    paper's adaptive rule); alpha = beta / (c dt) so nu = alpha dx = beta / CFL.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import line_sweep, weights
+
+ETA5 = (3, 2, 1, 0, -1)                      # node x_{i+m} <-> eta = -m
+SUB = ((3, 2, 1), (2, 1, 0), (1, 0, -1))     # substencils, as eta positions
+EPS_Z = 1e-6
+
+
+def weno5_coefficients(nu: float):
+    """(w5, c[3][3], d[3], residual): 5-point weights, substencil weights and linear weights."""
+    w5 = weights(nu, ETA5)
+    c = np.array([weights(nu, s) for s in SUB])
+    A = np.zeros((5, 3))
+    for r in range(3):
+        A[r:r + 3, r] = c[r]
+    d = np.linalg.lstsq(A, w5, rcond=None)[0]
+    return w5, c, d, float(np.abs(A @ d - w5).max())
+
+
+def smoothness(vals: np.ndarray) -> np.ndarray:
+    """beta_r of the quadratic through the 3 values of each substencil (last axis: the 5 stencil
+    values in ETA5 order), as the integral over the cell of the squared second derivative in
+    scaled units (dx^{2l-3} int (p^(l))^2 dx with l = 2)."""
+    out = []
+    for r, s in enumerate(SUB):
+        eta = np.array(s, dtype=float)
+        y = vals[..., r:r + 3]
+        # quadratic through (eta_j, y_j); its second eta-derivative is constant
+        V = np.vander(eta, 3)            # columns eta^2, eta, 1
+        coef = np.linalg.solve(V, np.moveaxis(y, -1, 0).reshape(3, -1))  # (3, m)
+        p2 = 2.0 * coef[0]               # d^2 p / d eta^2
+        # dx^{1} int_{cell} (d^2p/dx^2)^2 dx = int_0^1 (d^2 p / d eta^2)^2 d eta
+        out.append((p2 ** 2).reshape(y.shape[:-1]))
+    return np.stack(out, axis=-1)
+
+
+def wenoz_weights(beta: np.ndarray, d: np.ndarray, eps: float = EPS_Z) -> np.ndarray:
+    tau = np.abs(beta[..., 0] - beta[..., 2])[..., None]
+    wt = d * (1.0 + tau / (eps + beta))
+    return wt / wt.sum(axis=-1, keepdims=True)
+
+
+def stencils(v: np.ndarray, mirror: bool) -> np.ndarray:
+    """(n, 5) stencil values of a periodic line in ETA5 order: J_R uses x_{i+m}, m = -eta;
+    J_L the mirror x_{i-m}."""
+    n = v.size
+    idx = np.arange(n)[:, None]
+    m = -np.array(ETA5)[None, :]
+    return v[(idx - m) % n] if mirror else v[(idx + m) % n]
+
+
+def line_quad_weno(v: np.ndarray, nu: float, mode: str, omega=None):
+    """(JL, JR, omega_L, omega_R) of a periodic line; mode 'linear' | 'wenoz' | 'given' (omega =
+    (omega_L, omega_R) supplied by the caller)."""
+    _, c, d, _ = weno5_coefficients(nu)
+    res = []
+    for k, mirror in enumerate((True, False)):
+        S = stencils(v, mirror)
+        if mode == "linear":
+            om = np.broadcast_to(d, (v.size, 3))
+        elif mode == "wenoz":
+            om = wenoz_weights(smoothness(S), d)
+        else:
+            om = omega[k]
+        Jr = np.stack([S[:, r:r + 3] @ c[r] for r in range(3)], axis=-1)
+        res.append(((om * Jr).sum(axis=-1), om))
+    (JL, oL), (JR, oR) = res
+    return JL, JR, oL, oR
+
+
+def derivatives(v: np.ndarray, alpha: float, dx: float, mode: str, omega=None):
+    """(v-, v+) = (alpha D_R[v], -alpha D_L[v]) on a periodic line (Sec. 2.2, 2.3, 2.5)."""
+    n = v.size
+    JL, JR, _, _ = line_quad_weno(v, alpha * dx, mode, omega)
+    IL, IR, ends = line_sweep("periodic", alpha, dx, JL, JR)
+    d = math.exp(-alpha * dx)
+    mu = math.exp(-alpha * dx * n)
+    i = np.arange(n)
+    LR = IR + ends[1] / (1.0 - mu) * d ** i
+    LL = IL + ends[0] / (1.0 - mu) * d ** (n - i)
+    return alpha * (v - LR), -alpha * (v - LL)
+
+
+def hamiltonian_lf(pm, pp, qm, qp, rx, ry):
+    """Lax-Friedrichs numerical Hamiltonian of H(p, q) = (p^2 + q^2) / 2 (Sec. 2.5)."""
+    p, q = 0.5 * (pm + pp), 0.5 * (qm + qp)
+    return 0.5 * (p * p + q * q) + rx * 0.5 * (pm - pp) + ry * 0.5 * (qm - qp)
+
+
+def hj_run(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1.0, mode: str = "linear",
+           omega_fn=None, max_steps: int = 100000):
+    """Forward-Euler steps of u_t + (u_x^2 + u_y^2)/2 = 0 on a periodic [0, L]^2 grid (shape (ny, nx))
+    up to time T with the adaptive lagged rule.  omega_fn(stencils) -> weights for mode 'given'.
+    Returns (u, times, dts, (cx, cy) history)."""
+    u = np.array(u0, dtype=float)
+    ny, nx = u.shape
+    dx, dy = L / nx, L / ny
+    # initial wave speeds from the initial condition (no lag yet)
+    px = np.gradient(u, dx, axis=1)
+    py = np.gradient(u, dy, axis=0)
+    cx, cy = float(np.abs(px).max()), float(np.abs(py).max())
+    t, hist = 0.0, []
+    for _ in range(max_steps):
+        if t >= T - 1e-14:
+            break
+        dt = cfl * min(dx / max(cx, 1e-300), dy / max(cy, 1e-300))
+        dt = min(dt, T - t)
+        ax, ay = beta / (max(cx, 1e-300) * dt), beta / (max(cy, 1e-300) * dt)
+        pm = np.empty_like(u)
+        pp = np.empty_like(u)
+        qm = np.empty_like(u)
+        qp = np.empty_like(u)
+        for j in range(ny):
+            om = None if omega_fn is None else (omega_fn(stencils(u[j], True)), omega_fn(stencils(u[j], False)))
+            pm[j], pp[j] = derivatives(u[j], ax, dx, mode, om)
+        for i in range(nx):
+            col = u[:, i].copy()
+            om = None if omega_fn is None else (omega_fn(stencils(col, True)), omega_fn(stencils(col, False)))
+            qm[:, i], qp[:, i] = derivatives(col, ay, dy, mode, om)
+        Hh = hamiltonian_lf(pm, pp, qm, qp, cx, cy)
+        u = u - dt * Hh
+        t += dt
+        # wave speeds for the next step (lagged): max |H_p| = max |u_x| over both one-sided values
+        cx = float(max(np.abs(pm).max(), np.abs(pp).max()))
+        cy = float(max(np.abs(qm).max(), np.abs(qp).max()))
+        hist.append((t, dt, cx, cy))
+    return u, hist
+
+
+def hopf_lax_1d(x: np.ndarray, t: float, nquad: int = 20001) -> np.ndarray:
+    """Viscosity solution of w_t + w_x^2 / 2 = 0, w(x, 0) = sin x: w(x, t) = min_y sin y + (x - y)^2 / (2t),
+    minimised over a fine grid around every x and refined by golden-section search."""
+    if t == 0.0:
+        return np.sin(x)
+    out = np.empty_like(x)
+    span = math.pi * 1.05 + t
+    ys = np.linspace(-span, span, nquad)
+    for k, xv in enumerate(x):
+        f = np.sin(xv + ys) + ys ** 2 / (2 * t)
+        j = int(np.argmin(f))
+        a, b = xv + ys[max(j - 1, 0)], xv + ys[min(j + 1, nquad - 1)]
+        g = (math.sqrt(5) - 1) / 2
+        fn = lambda y: math.sin(y) + (xv - y) ** 2 / (2 * t)
+        c, d_ = b - g * (b - a), a + g * (b - a)
+        for _ in range(80):
+            if fn(c) < fn(d_):
+                b = d_
+            else:
+                a = c
+            c, d_ = b - g * (b - a), a + g * (b - a)
+        out[k] = fn(0.5 * (a + b))
+    return out
+
+
+def exact_solution(nx: int, ny: int, L: float, t: float) -> np.ndarray:
+    """u = w(x, t) + w(y, t) for u0 = sin x + sin y (the Hamiltonian separates)."""
+    x = np.arange(nx) * (L / nx)
+    y = np.arange(ny) * (L / ny)
+    return hopf_lax_1d(y, t)[:, None] + hopf_lax_1d(x, t)[None, :]
