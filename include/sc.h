@@ -186,6 +186,55 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
 /* JSON description of the plan's launches and tile shapes; returns its length (buf may be NULL). */
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
 
+/* ------------------------------------------------------------------------------------------------
+ * Nonlinear Hamilton-Jacobi equation u_t + (u_x^2 + u_y^2) / 2 = 0 on a periodic 2-D grid (FP64,
+ * shape (n[1], n[0])), first order in time (Sec. 2.5): u <- u - dt H^ with the Lax-Friedrichs
+ * numerical Hamiltonian H^ of the one-sided derivatives u_x^- = alpha D_R[u], u_x^+ = -alpha D_L[u]
+ * (and likewise in y).  The local integrals use a 5-point WENO quadrature built from three 3-point
+ * substencils (Sec. 2.4) with
+ *   weights = 0: the linear weights d_r (smooth data),
+ *             1: WENO-Z nonlinear weights (smoothness: squared second difference per substencil),
+ *             2: weights proposed by the learned MLP (sc_mlp_*), each proposal judged against the
+ *                WENO-Z weights and replaced by them when some weight differs by more than theta.
+ * Adaptive step with one lagged wave speed c (held on the device): dt = cfl min(dx, dy) / c, the
+ * last step shortened to land on t_end; alpha = beta / (cfl min(dx, dy)) on both axes; the LF
+ * dissipation is c; c is then replaced by the largest one-sided derivative of the step.
+ * state (device, 8 doubles): [c, t, steps, fallbacks, summed judged error, proposals judged, -, -].
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct {
+    double beta;      /* > 0 */
+    double cfl;       /* > 0 */
+    double t_end;     /* steps stop advancing past t_end */
+    double theta;     /* learned weights: largest accepted |proposal - WENO-Z| per weight */
+    int32_t weights;  /* 0 linear, 1 WENO-Z, 2 learned */
+    int32_t reserved; /* 0 */
+} sc_hj_params;
+
+size_t sc_hj_workspace_bytes(const sc_grid *grid);
+/* state <- initial wave speed (max of periodic central differences of u), t = 0, counters 0. */
+sc_status sc_hj_init(const sc_grid *grid, const sc_hj_params *p, const void *u, double *state, void *ws,
+                     size_t ws_bytes, sc_stream_t stream);
+/* nsteps steps in place (no host synchronisation: dt is read from state on the device).
+ * mlp_params: device FP32 parameters of the proposer (weights = 2), else may be NULL. */
+sc_status sc_hj_step(const sc_grid *grid, const sc_hj_params *p, int nsteps, void *u, double *state,
+                     const float *mlp_params, void *ws, size_t ws_bytes, sc_stream_t stream);
+/* Training samples from a field: for every point and side (rows 2p: J_R stencil, 2p + 1: J_L) the
+ * proposer's 8 features (X, FP32) and the WENO-Z weights (Y, 3 FP32) along `axis`. */
+sc_status sc_hj_harvest(const sc_grid *grid, const sc_hj_params *p, const void *u, int axis, float *X, float *Y,
+                        sc_stream_t stream);
+
+/* The proposer: features (8) -> 32 -> 32 -> 3 with ReLU and softmax; FP32 master parameters on
+ * the device, row-major (out, in) weights each followed by its bias (W1 b1 W2 b2 W3 b3); the matrix
+ * products run on the matrix cores with BF16 operands and FP32 accumulation. */
+int sc_mlp_param_count(void);
+sc_status sc_mlp_forward(const float *params, int64_t n, const float *X, float *Y, sc_stream_t stream);
+size_t sc_mlp_grad_workspace_bytes(int64_t n);
+/* grad = d loss / d params, loss = mean over the n samples of sum_r (omega_r - Y_r)^2 (device). */
+sc_status sc_mlp_grad(const float *params, int64_t n, const float *X, const float *Y, float *grad, float *loss,
+                      void *ws, size_t ws_bytes, sc_stream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); step >= 1 is the update count. */
+sc_status sc_mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, sc_stream_t stream);
+
 /* Optional per-kernel timing with HIP events recorded on the caller's stream around every launch
  * the library makes (for benchmarks).  sc_timing_read returns the number of kernel names written;
  * ms[i] is the summed elapsed time and counts[i] the launches of names[i] since the last reset.

@@ -20,8 +20,11 @@ for the details):
     eps = 1e-6, normalised to sum 1.
   * Lax-Friedrichs Hamiltonian (Sec. 2.5): H^(v-, v+) = H((v- + v+)/2) + r (v- - v+)/2 per axis,
     r = the global max |H_p| (lagged), with v- = alpha D_R[u], v+ = -alpha D_L[u] (s = 1).
-  * Adaptive step: dt = CFL min(dx / c_x, dy / c_y) with lagged wave speeds c = max |u_x| (the
-    paper's adaptive rule); alpha = beta / (c dt) so nu = alpha dx = beta / CFL.
+  * Adaptive step (the paper's adaptive rule with one lagged wave speed, as its adaptive examples
+    keep the wave speeds symmetric): c = max over both axes of the one-sided derivatives of the
+    previous step (initially of periodic central differences of u0), dt = CFL min(dx, dy) / c,
+    alpha = beta / (c dt) = beta / (CFL min(dx, dy)) on both axes -- constant, so the quadrature
+    weights are fixed -- and the Lax-Friedrichs coefficient r = c on both axes.
 """
 from __future__ import annotations
 
@@ -120,22 +123,22 @@ def hamiltonian_lf(pm, pp, qm, qp, rx, ry):
 def hj_run(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1.0, mode: str = "linear",
            omega_fn=None, max_steps: int = 100000):
     """Forward-Euler steps of u_t + (u_x^2 + u_y^2)/2 = 0 on a periodic [0, L]^2 grid (shape (ny, nx))
-    up to time T with the adaptive lagged rule.  omega_fn(stencils) -> weights for mode 'given'.
-    Returns (u, times, dts, (cx, cy) history)."""
+    up to time T (the last step shortened to land on T) with the adaptive lagged rule.
+    omega_fn(stencils) -> weights for mode 'given'.  Returns (u, [(t, dt, c) per step])."""
     u = np.array(u0, dtype=float)
     ny, nx = u.shape
     dx, dy = L / nx, L / ny
-    # initial wave speeds from the initial condition (no lag yet)
-    px = np.gradient(u, dx, axis=1)
-    py = np.gradient(u, dy, axis=0)
-    cx, cy = float(np.abs(px).max()), float(np.abs(py).max())
+    h = min(dx, dy)
+    # initial wave speed from the initial condition (no lag yet): periodic central differences
+    px = (np.roll(u, -1, axis=1) - np.roll(u, 1, axis=1)) / (2 * dx)
+    py = (np.roll(u, -1, axis=0) - np.roll(u, 1, axis=0)) / (2 * dy)
+    c = float(max(np.abs(px).max(), np.abs(py).max()))
     t, hist = 0.0, []
+    ax = ay = beta / (cfl * h)
     for _ in range(max_steps):
         if t >= T - 1e-14:
             break
-        dt = cfl * min(dx / max(cx, 1e-300), dy / max(cy, 1e-300))
-        dt = min(dt, T - t)
-        ax, ay = beta / (max(cx, 1e-300) * dt), beta / (max(cy, 1e-300) * dt)
+        dt = min(cfl * h / c, T - t)
         pm = np.empty_like(u)
         pp = np.empty_like(u)
         qm = np.empty_like(u)
@@ -147,13 +150,12 @@ def hj_run(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1
             col = u[:, i].copy()
             om = None if omega_fn is None else (omega_fn(stencils(col, True)), omega_fn(stencils(col, False)))
             qm[:, i], qp[:, i] = derivatives(col, ay, dy, mode, om)
-        Hh = hamiltonian_lf(pm, pp, qm, qp, cx, cy)
+        Hh = hamiltonian_lf(pm, pp, qm, qp, c, c)
         u = u - dt * Hh
         t += dt
-        # wave speeds for the next step (lagged): max |H_p| = max |u_x| over both one-sided values
-        cx = float(max(np.abs(pm).max(), np.abs(pp).max()))
-        cy = float(max(np.abs(qm).max(), np.abs(qp).max()))
-        hist.append((t, dt, cx, cy))
+        # wave speed for the next step (lagged): max |H_p|, |H_q| over the one-sided derivatives
+        c = float(max(np.abs(pm).max(), np.abs(pp).max(), np.abs(qm).max(), np.abs(qp).max()))
+        hist.append((t, dt, c))
     return u, hist
 
 

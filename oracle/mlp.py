@@ -6,11 +6,13 @@ kernels round (matrix-core operands).
 TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT (only ``tests/``, ``__graft_entry__.smoke()`` and
 ``bench.py``'s ``cpu_baseline`` leg may use it).
 
-Feature map (written out again, independently, in the HIP kernels): for the stencil values s_0..s_4
-(ETA5 order of ``oracle.hj``), m = mean(s), sigma = max_j |s_j - m|;
-  f_j = (s_j - m) / sigma (j < 5; 0 when sigma = 0),
-  f_5 = clip(log10(sigma^2 / 1e-6), -8, 8) / 8    (the scale against the WENO-Z epsilon),
-  f_6 = f_7 = 0 (padding).
+Feature map (written out again, independently, in the HIP kernels), from the stencil values
+s_0..s_4 (ETA5 order of ``oracle.hj``): the substencils' second differences q_r = s_r - 2 s_{r+1} +
+s_{r+2} (r = 0, 1, 2) and Q = max_r |q_r|, the deviations from the centre value e_k = s_k - s_2 and
+E = max_k |e_k|:
+  f_0..f_2 = q_r / Q                                 (0 when Q = 0)
+  f_3      = clip(log10(Q^2 / 1e-6), -8, 8) / 8      (the scale against the WENO-Z epsilon; -1 when Q = 0)
+  f_4..f_7 = e_k / E for k = 0, 1, 3, 4              (0 when E = 0)
 """
 from __future__ import annotations
 
@@ -31,23 +33,23 @@ def bf16(a: np.ndarray) -> np.ndarray:
 
 def features(S: np.ndarray) -> np.ndarray:
     S = np.asarray(S, dtype=float)
-    m = S.mean(axis=-1, keepdims=True)
-    dev = S - m
-    sig = np.abs(dev).max(axis=-1, keepdims=True)
+    q = np.stack([S[..., r] - 2.0 * S[..., r + 1] + S[..., r + 2] for r in range(3)], axis=-1)
+    Q = np.abs(q).max(axis=-1, keepdims=True)
+    e = S - S[..., 2:3]
+    E = np.abs(e).max(axis=-1, keepdims=True)
     f = np.zeros(S.shape[:-1] + (NIN,))
-    safe = np.where(sig > 0, sig, 1.0)
-    f[..., :5] = np.where(sig > 0, dev / safe, 0.0)
+    f[..., 0:3] = np.where(Q > 0, q / np.where(Q > 0, Q, 1.0), 0.0)
     with np.errstate(divide="ignore"):
-        lg = np.log10(np.where(sig[..., 0] > 0, sig[..., 0] ** 2 / EPS_Z, 1e-300))
-    f[..., 5] = np.clip(lg, -8.0, 8.0) / 8.0
+        lg = np.log10(np.where(Q[..., 0] > 0, Q[..., 0] ** 2 / EPS_Z, 1e-300))
+    f[..., 3] = np.clip(lg, -8.0, 8.0) / 8.0
+    f[..., 4:8] = np.where(E > 0, e[..., [0, 1, 3, 4]] / np.where(E > 0, E, 1.0), 0.0)
     return f
 
 
 def init_params(seed: int = 0):
     """He-initialised weights (W: (out, in)), zero biases."""
     g = np.random.default_rng(seed)
-    W1 = g.standard_normal((NH, NIN)) * np.sqrt(2.0 / 6)
-    W1[:, 6:] = 0.0
+    W1 = g.standard_normal((NH, NIN)) * np.sqrt(2.0 / NIN)
     W2 = g.standard_normal((NH, NH)) * np.sqrt(2.0 / NH)
     W3 = g.standard_normal((NOUT, NH)) * np.sqrt(1.0 / NH)
     return dict(W1=W1, b1=np.zeros(NH), W2=W2, b2=np.zeros(NH), W3=W3, b3=np.zeros(NOUT))

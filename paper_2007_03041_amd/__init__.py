@@ -32,7 +32,8 @@ SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_
            "sc_timing_enable", "sc_timing_read", "sc_timing_reset",
            "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_workspace_bytes",
            "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
-           "sc_batch_describe")
+           "sc_batch_describe", "sc_hj_workspace_bytes", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
+           "sc_mlp_param_count", "sc_mlp_forward", "sc_mlp_grad_workspace_bytes", "sc_mlp_grad", "sc_mlp_adam")
 
 
 class ScError(RuntimeError):
@@ -56,6 +57,14 @@ class sc_batch_item(ctypes.Structure):
     _fields_ = [("offset", c_int64), ("n", c_int64), ("nlines", c_int64), ("lo", c_double), ("hi", c_double),
                 ("alpha", c_double), ("scale", c_double), ("g_offset", c_int64), ("bc", c_int32),
                 ("op", c_int32), ("k", c_int32), ("reserved", c_int32)]
+
+
+class sc_hj_params(ctypes.Structure):
+    _fields_ = [("beta", c_double), ("cfl", c_double), ("t_end", c_double), ("theta", c_double),
+                ("weights", c_int32), ("reserved", c_int32)]
+
+
+HJ_WEIGHTS = {"linear": 0, "wenoz": 1, "learned": 2}
 
 
 @dataclass
@@ -131,9 +140,24 @@ def load():
     lib.sc_batch_tune.argtypes = [bp, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
     lib.sc_batch_describe.argtypes = [bp, c_char_p, c_int]
     lib.sc_batch_describe.restype = c_int
+    hp = POINTER(sc_hj_params)
+    lib.sc_hj_workspace_bytes.argtypes = [gp]
+    lib.sc_hj_workspace_bytes.restype = c_size_t
+    lib.sc_hj_init.argtypes = [gp, hp, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.sc_hj_step.argtypes = [gp, hp, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.sc_hj_harvest.argtypes = [gp, hp, c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    lib.sc_mlp_param_count.argtypes = []
+    lib.sc_mlp_param_count.restype = c_int
+    lib.sc_mlp_forward.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.sc_mlp_grad_workspace_bytes.argtypes = [c_int64]
+    lib.sc_mlp_grad_workspace_bytes.restype = c_size_t
+    lib.sc_mlp_grad.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                c_void_p]
+    lib.sc_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]
     for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum", "sc_time_step",
               "sc_timing_enable", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
-              "sc_batch_apply_per_instance", "sc_batch_tune"):
+              "sc_batch_apply_per_instance", "sc_batch_tune", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
+              "sc_mlp_forward", "sc_mlp_grad", "sc_mlp_adam"):
         getattr(lib, f).restype = c_int
     _lib = lib
     return lib
@@ -397,3 +421,138 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------------------------
+# Nonlinear Hamilton-Jacobi example and the learned weight proposer
+# ------------------------------------------------------------------------------------------------
+def _f32dev(t, name, shape_last=None):
+    import torch
+
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name}: contiguous float32 device tensor")
+    if shape_last is not None and t.shape[-1] != shape_last:
+        raise ValueError(f"{name}: last dimension must be {shape_last}")
+
+
+class HJSolver:
+    """u_t + |grad u|^2 / 2 = 0 on a periodic n x n grid of [0, L]^2 (``sc_hj_*``); u is an (n1, n0)
+    float64 device tensor updated in place."""
+
+    def __init__(self, n, L=2 * 3.141592653589793, beta=1.0, cfl=1.0, t_end=1.0, weights="linear",
+                 theta=0.05, device="cuda"):
+        import torch
+
+        n0, n1 = (n, n) if isinstance(n, int) else n
+        self.grid = Grid((n0, n1), (0.0, 0.0), (L, L))
+        self._gc = self.grid.c()
+        self.p = sc_hj_params()
+        self.p.beta, self.p.cfl, self.p.t_end, self.p.theta = beta, cfl, t_end, theta
+        self.p.weights, self.p.reserved = HJ_WEIGHTS[weights], 0
+        lib = load()
+        nb = int(lib.sc_hj_workspace_bytes(ctypes.byref(self._gc)))
+        if nb == 0:
+            raise ScError(SC_ERR_ARG, "invalid grid")
+        self._ws, self._wsp = _workspace(nb, device)
+        self._nbytes = nb - 256
+        self.state = torch.zeros(8, dtype=torch.float64, device=device)
+        self.mlp = None
+
+    def init(self, u):
+        _tensor_ok(u, self.grid, "u")
+        _check(load().sc_hj_init(ctypes.byref(self._gc), ctypes.byref(self.p), u.data_ptr(), self.state.data_ptr(),
+                                 self._wsp, self._nbytes, _stream()))
+
+    def step(self, u, nsteps=1):
+        _tensor_ok(u, self.grid, "u")
+        mp = None
+        if self.p.weights == 2:
+            if self.mlp is None:
+                raise ValueError("learned weights: set .mlp to the proposer's parameters")
+            _f32dev(self.mlp, "mlp")
+            mp = self.mlp.data_ptr()
+        _check(load().sc_hj_step(ctypes.byref(self._gc), ctypes.byref(self.p), nsteps, u.data_ptr(),
+                                 self.state.data_ptr(), mp, self._wsp, self._nbytes, _stream()))
+        return u
+
+    def run_to(self, u, max_steps=100000, chunk=16):
+        """Steps until the device-side time reaches t_end (checks every ``chunk`` steps)."""
+        self.init(u)
+        done = 0
+        while done < max_steps:
+            self.step(u, chunk)
+            done += chunk
+            if self.read_state()["t"] >= self.p.t_end - 1e-14:
+                break
+        return u
+
+    def read_state(self):
+        import torch
+
+        torch.cuda.synchronize()
+        s = self.state.cpu().tolist()
+        return dict(c=s[0], t=s[1], steps=int(s[2]), fallbacks=s[3], judged_err_sum=s[4], judged=s[5])
+
+    def harvest(self, u, axis):
+        """(X, Y): features and WENO-Z weights of every stencil of u along ``axis`` (2 per point)."""
+        import torch
+
+        _tensor_ok(u, self.grid, "u")
+        n = u.numel()
+        X = torch.empty((2 * n, 8), dtype=torch.float32, device=u.device)
+        Y = torch.empty((2 * n, 3), dtype=torch.float32, device=u.device)
+        _check(load().sc_hj_harvest(ctypes.byref(self._gc), ctypes.byref(self.p), u.data_ptr(), axis, X.data_ptr(),
+                                    Y.data_ptr(), _stream()))
+        return X, Y
+
+
+def mlp_param_count() -> int:
+    return int(load().sc_mlp_param_count())
+
+
+def mlp_forward(params, X):
+    import torch
+
+    _f32dev(params, "params")
+    _f32dev(X, "X", 8)
+    Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device=X.device)
+    _check(load().sc_mlp_forward(params.data_ptr(), X.shape[0], X.data_ptr(), Y.data_ptr(), _stream()))
+    return Y
+
+
+class MlpTrainer:
+    """Gradient and Adam state of the proposer (all arithmetic in the library's kernels)."""
+
+    def __init__(self, params, max_batch: int):
+        import torch
+
+        _f32dev(params, "params")
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        nb = int(load().sc_mlp_grad_workspace_bytes(max_batch))
+        self._ws = torch.empty(nb // 4 + 64, dtype=torch.float32, device=params.device)
+        self._nbytes = nb
+        self.max_batch = max_batch
+        self.t = 0
+
+    def gradient(self, X, Y):
+        _f32dev(X, "X", 8)
+        _f32dev(Y, "Y", 3)
+        if X.shape[0] > self.max_batch:
+            raise ValueError("batch larger than max_batch")
+        _check(load().sc_mlp_grad(self.params.data_ptr(), X.shape[0], X.data_ptr(), Y.data_ptr(), self.grad.data_ptr(),
+                                  self.loss.data_ptr(), self._ws.data_ptr(), self._nbytes, _stream()))
+        return self.grad, self.loss
+
+    def adam(self, lr: float):
+        self.t += 1
+        _check(load().sc_mlp_adam(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                  self.t, float(lr), _stream()))
+
+    def step(self, X, Y, lr: float):
+        self.gradient(X, Y)
+        self.adam(lr)
+        return self.loss

@@ -120,7 +120,7 @@ double last_part_decay(double nu, int64_t n_loc, const scx::Variant &V)
 }
 
 // Per-(axis, operator, alpha) constants for the variant chosen for the pass.
-void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid, double scale, int k)
+void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid, double scale, int k, int identity)
 {
     std::memset(P, 0, sizeof(*P));
     const scx::Variant &V = scx::variant(vid);
@@ -129,7 +129,12 @@ void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, in
     int eta[8];
     // interior: window offset j <-> node x_{i-H+j} <-> eta = H - j (J_R); J_L uses the mirror
     for (int j = 0; j < order; ++j) eta[j] = H - j;
-    scx::quad_weights(nu, order, eta, P->wR);
+    if (identity) {
+        // the operand is the local integral itself: J_R[i] = v[i] and, by the mirror layout, J_L[i] = v[i]
+        for (int j = 0; j < order; ++j) P->wR[j] = (j == H) ? 1.0 : 0.0;
+    } else {
+        scx::quad_weights(nu, order, eta, P->wR);
+    }
     const int S = V.S;
     // segment totals as linear functionals of the window (S + order values):
     //   sum_t d^{S-1-t} J_R[t] = sum_w kR[w] win[w],  J_R[t] = sum_j wR[j] win[t+j]
@@ -229,7 +234,7 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     fill_ext(&a, order);
     bool multi = false;
     for (int o = 0; o < nops; ++o) {
-        fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, vid, ops[o].scale, ops[o].k);
+        fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, vid, ops[o].scale, ops[o].k, ops[o].identity);
         multi = multi || ops[o].k > 1;
     }
     if (multi && (nops != 1 || a.nchunks != 1 || ax.bc != SC_BC_PERIODIC || acc_mode != 0))

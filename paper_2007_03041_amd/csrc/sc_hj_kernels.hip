@@ -1,0 +1,824 @@
+// sc_hj_kernels.hip -- kernels of the nonlinear Hamilton-Jacobi example (u_t + |grad u|^2 / 2 = 0, periodic,
+// 2-D) and of the learned quadrature-weight proposer.
+//
+//   hj_weno_quad     per point: the two 5-point local integrals J_L, J_R along one axis from three
+//                    3-point substencils (Sec. 2.4) with linear, WENO-Z or proposed weights; the
+//                    proposer is a 3-layer MLP evaluated on the matrix cores (BF16 operands, FP32
+//                    accumulation), its proposal judged against the WENO-Z weights and replaced by
+//                    them when it is off by more than a threshold
+//   hj_update        per point: the Lax-Friedrichs numerical Hamiltonian of the one-sided
+//                    derivatives (Sec. 2.5) and the forward-Euler update, with the time step and the
+//                    dissipation taken from the lagged wave speed held on the device
+//   hj_finish_step   reduces the new wave speed and advances the device-side time (the paper's
+//                    adaptive rule: the reduction of one step feeds the next)
+//   mlp_forward / mlp_train_tile / mlp_reduce_grads / mlp_adam: inference and training of the proposer
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc_hj_dev.h"
+
+namespace scx {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------------------------------
+// The proposer on the matrix cores.  A 16x16x16 product: lane l = 16 g + m holds A[m][4g..4g+3],
+// B[4g..4g+3][m] and the result D[4g..4g+3][m].  Weights are read into B operands once per wave:
+// B[k][n] = W[n][k] for W stored (out, in) row-major.
+// ------------------------------------------------------------------------------------------
+struct MlpOperands {
+    bf16x4 w1[2];     // layer 1: N-tiles 0, 1 (K = 16, features 0..7 real)
+    bf16x4 w2[2][2];  // layer 2: [N-tile][K-step]
+    bf16x4 w3[2];     // layer 3: [K-step] (N = 3 real of 16)
+    float b1[2], b2[2], b3;
+};
+
+__device__ __forceinline__ MlpOperands mlp_load(const float *__restrict__ P, int lane)
+{
+    MlpOperands o;
+    const int m = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int n = 16 * t + m;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            o.w1[t][j] = k < MLP_IN ? f2bf(P[MLP_W1 + n * MLP_IN + k]) : (short)0;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o.w2[t][s][j] = f2bf(P[MLP_W2 + n * MLP_H + 16 * s + 4 * g + j]);
+        o.b1[t] = P[MLP_B1 + n];
+        o.b2[t] = P[MLP_B2 + n];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o.w3[s][j] = m < MLP_OUT ? f2bf(P[MLP_W3 + m * MLP_H + 16 * s + 4 * g + j]) : (short)0;
+    o.b3 = m < MLP_OUT ? P[MLP_B3 + m] : 0.f;
+    return o;
+}
+
+// Forward of 16 samples whose features are rows feat[0..15][0..7] (LDS).  hid: 16 x 33 LDS
+// scratch of the calling wave; the logits go to z[0..15][0..3] (LDS).  Every lane of the wave calls
+// it; `bar` synchronises the writers and readers of the scratch.  If keep != nullptr the layer
+// inputs and pre-activations are copied there for the backward pass (keep: z1[16][33], h1[16][33],
+// z2[16][33], h2[16][33]).
+template <typename Bar>
+__device__ __forceinline__ void mlp_tile_forward(const MlpOperands &o, const float (*feat)[MLP_IN], float (*hid)[33],
+                                                 float (*z)[4], float (*keep)[16][33], int lane, Bar bar)
+{
+    const int m = lane & 15, g = lane >> 4;
+    bf16x4 a;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = (4 * g + j) < MLP_IN ? f2bf(feat[m][4 * g + j]) : (short)0;
+    f32x4 z1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const f32x4 c = {o.b1[t], o.b1[t], o.b1[t], o.b1[t]};
+        z1[t] = mfma16(a, o.w1[t], c);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            hid[4 * g + j][16 * t + m] = fmaxf(z1[t][j], 0.f);
+            if (keep) keep[0][4 * g + j][16 * t + m] = z1[t][j];
+        }
+    bar();
+    bf16x4 a2[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a2[s][j] = f2bf(hid[m][16 * s + 4 * g + j]);
+    bar();
+    f32x4 z2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const f32x4 c = {o.b2[t], o.b2[t], o.b2[t], o.b2[t]};
+        z2[t] = mfma16(a2[0], o.w2[t][0], c);
+        z2[t] = mfma16(a2[1], o.w2[t][1], z2[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            hid[4 * g + j][16 * t + m] = fmaxf(z2[t][j], 0.f);
+            if (keep) keep[2][4 * g + j][16 * t + m] = z2[t][j];
+        }
+    bar();
+    bf16x4 a3[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a3[s][j] = f2bf(hid[m][16 * s + 4 * g + j]);
+    bar();
+    const f32x4 c3 = {o.b3, o.b3, o.b3, o.b3};
+    f32x4 z3 = mfma16(a3[0], o.w3[0], c3);
+    z3 = mfma16(a3[1], o.w3[1], z3);
+    if (m < MLP_OUT)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z[4 * g + j][m] = z3[j];
+    bar();
+}
+
+__device__ __forceinline__ void softmax3(const float *zz, double *om)
+{
+    const double a = zz[0], b = zz[1], c = zz[2];
+    const double mx = fmax(a, fmax(b, c));
+    const double ea = exp(a - mx), eb = exp(b - mx), ec = exp(c - mx);
+    const double s = ea + eb + ec;
+    om[0] = ea / s;
+    om[1] = eb / s;
+    om[2] = ec / s;
+}
+
+// Features of a 5-point stencil (ETA5 order): the substencils' second differences over their
+// largest magnitude, that magnitude against the WENO-Z epsilon (log scale), and the deviations of
+// the outer values from the centre value over their largest magnitude.
+__device__ __forceinline__ void stencil_features(const double *s, float *f)
+{
+    double q[3], Q = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        q[r] = s[r] - 2.0 * s[r + 1] + s[r + 2];
+        Q = fmax(Q, fabs(q[r]));
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) f[r] = Q > 0.0 ? (float)(q[r] / Q) : 0.f;
+    double lg = Q > 0.0 ? log10(Q * Q / HJ_EPS_Z) : -8.0;
+    lg = fmin(fmax(lg, -8.0), 8.0);
+    f[3] = (float)(lg / 8.0);
+    const double e[4] = {s[0] - s[2], s[1] - s[2], s[3] - s[2], s[4] - s[2]};
+    double E = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) E = fmax(E, fabs(e[k]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[4 + k] = E > 0.0 ? (float)(e[k] / E) : 0.f;
+}
+
+// WENO-Z weights of a 5-point stencil: smoothness = squared second difference per substencil.
+__device__ __forceinline__ void wenoz(const double *s, const double *d, double *om)
+{
+    double beta[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double q = s[r] - 2.0 * s[r + 1] + s[r + 2];
+        beta[r] = q * q;
+    }
+    const double tau = fabs(beta[0] - beta[2]);
+    double sum = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        om[r] = d[r] * (1.0 + tau / (HJ_EPS_Z + beta[r]));
+        sum += om[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) om[r] /= sum;
+}
+
+// ------------------------------------------------------------------------------------------
+// hj_weno_quad: block of 256 points (4 waves); each point has two stencils (J_R: nodes
+// x_{i-3}..x_{i+1}; J_L: the mirror x_{i+3}..x_{i-1}).
+// ------------------------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u, double *__restrict__ JL,
+                                                    double *__restrict__ JR, const HjQuadArgs A,
+                                                    const float *__restrict__ P, double *__restrict__ stats)
+{
+    __shared__ float feat[512][MLP_IN];
+    __shared__ float hid[4][16][33];
+    __shared__ float zo[512][4];
+    __shared__ double red[2][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    const bool ok = p < A.nx * A.ny;
+    const int64_t pj = ok ? p / A.nx : 0, pi = ok ? p % A.nx : 0;
+    double v[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        int64_t idx;
+        if (A.axis == 0) {
+            int64_t i2 = pi + (k - 3);
+            i2 = i2 < 0 ? i2 + A.nx : (i2 >= A.nx ? i2 - A.nx : i2);
+            idx = pj * A.nx + i2;
+        } else {
+            int64_t j2 = pj + (k - 3);
+            j2 = j2 < 0 ? j2 + A.ny : (j2 >= A.ny ? j2 - A.ny : j2);
+            idx = j2 * A.nx + pi;
+        }
+        v[k] = ok ? u[idx] : 0.0;
+    }
+    double sR[5], sL[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        sR[k] = v[k];      // node offset k - 3
+        sL[k] = v[6 - k];  // mirror: offset 3 - k
+    }
+    double oR[3], oL[3];
+    double err_sum = 0.0, nfall = 0.0;
+    if (MODE == HJ_LINEAR) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) oR[r] = oL[r] = A.d[r];
+    } else {
+        wenoz(sR, A.d, oR);
+        wenoz(sL, A.d, oL);
+    }
+    if (MODE == HJ_LEARNED) {
+        stencil_features(sR, feat[tid]);
+        stencil_features(sL, feat[256 + tid]);
+        __syncthreads();
+        const MlpOperands o = mlp_load(P, lane);
+        auto bar = [] { __syncthreads(); };
+        for (int T = 0; T < 8; ++T) {
+            const int base = (T >> 2) * 256 + wv * 64 + 16 * (T & 3);
+            mlp_tile_forward(o, &feat[base], hid[wv], &zo[base], (float(*)[16][33]) nullptr, lane, bar);
+        }
+        double pR[3], pL[3];
+        softmax3(zo[tid], pR);
+        softmax3(zo[256 + tid], pL);
+        double eR = 0.0, eL = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            eR = fmax(eR, fabs(pR[r] - oR[r]));
+            eL = fmax(eL, fabs(pL[r] - oL[r]));
+        }
+        if (ok) {
+            err_sum = eR + eL;
+            nfall = (eR > A.theta ? 1.0 : 0.0) + (eL > A.theta ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (eR <= A.theta) oR[r] = pR[r];
+            if (eL <= A.theta) oL[r] = pL[r];
+        }
+        // per-block statistics: proposals judged, fallbacks, summed judged error
+        red[0][tid] = nfall;
+        red[1][tid] = err_sum;
+        __syncthreads();
+        for (int sft = 128; sft > 0; sft >>= 1) {
+            if (tid < sft) {
+                red[0][tid] += red[0][tid + sft];
+                red[1][tid] += red[1][tid + sft];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int64_t nb = blockIdx.x;
+            stats[3 * nb + 0] = red[0][0];
+            stats[3 * nb + 1] = red[1][0];
+            stats[3 * nb + 2] = (double)(((int64_t)A.nx * A.ny - (int64_t)blockIdx.x * 256) < 256
+                                             ? 2 * ((int64_t)A.nx * A.ny - (int64_t)blockIdx.x * 256)
+                                             : 512);
+        }
+    }
+    if (!ok) return;
+    double jr = 0.0, jl = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double qR = 0.0, qL = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            qR = fma(A.c[r][j], sR[r + j], qR);
+            qL = fma(A.c[r][j], sL[r + j], qL);
+        }
+        jr = fma(oR[r], qR, jr);
+        jl = fma(oL[r], qL, jl);
+    }
+    JR[p] = jr;
+    JL[p] = jl;
+}
+
+// ------------------------------------------------------------------------------------------
+// Update and the adaptive rule
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double hj_dt(const HjStepArgs &A, const double *state)
+{
+    double dt = A.cfl_h / state[HJ_S_C];
+    const double left = A.t_end - state[HJ_S_T];
+    return dt < left ? dt : (left > 0.0 ? left : 0.0);
+}
+
+// u <- u - dt H^(p-, p+, q-, q+); D* hold u - L^{-1}[u] from the sweeps: p- = alpha Dm, p+ = -alpha Dp
+__global__ void __launch_bounds__(256) hj_update(double *__restrict__ u, const double *__restrict__ DmX,
+                                                 const double *__restrict__ DpX, const double *__restrict__ DmY,
+                                                 const double *__restrict__ DpY, const HjStepArgs A,
+                                                 const double *__restrict__ state, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    const double c = state[HJ_S_C];
+    const double dt = hj_dt(A, state);
+    double m = 0.0;
+    if (p < A.npts) {
+        const double pm = A.alpha_x * DmX[p], pp = -A.alpha_x * DpX[p];
+        const double qm = A.alpha_y * DmY[p], qp = -A.alpha_y * DpY[p];
+        const double px = 0.5 * (pm + pp), qy = 0.5 * (qm + qp);
+        const double H = 0.5 * (px * px + qy * qy) + c * 0.5 * (pm - pp) + c * 0.5 * (qm - qp);
+        u[p] = u[p] - dt * H;
+        m = fmax(fmax(fabs(pm), fabs(pp)), fmax(fabs(qm), fabs(qp)));
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+// Initial wave speed: max over periodic central differences of u0 along both axes.
+__global__ void __launch_bounds__(256) hj_init_speed(const double *__restrict__ u, const HjStepArgs A,
+                                                     double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    double m = 0.0;
+    if (p < A.npts) {
+        const int64_t j = p / A.nx, i = p % A.nx;
+        const int64_t ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
+        const int64_t jp = j + 1 == A.ny ? 0 : j + 1, jm = j == 0 ? A.ny - 1 : j - 1;
+        const double gx = (u[j * A.nx + ip] - u[j * A.nx + im]) / (2.0 * A.dx);
+        const double gy = (u[jp * A.nx + i] - u[jm * A.nx + i]) / (2.0 * A.dy);
+        m = fmax(fabs(gx), fabs(gy));
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+// One block: reduce the per-block maxima (and the proposer statistics), then advance the state.
+// mode 0: initialise (c = max, t = 0, counters = 0); mode 1: after an update (t += dt with the old c,
+// then c = max).
+__global__ void __launch_bounds__(256) hj_finish_step(const double *__restrict__ part, int64_t nparts,
+                                                      const double *__restrict__ stats, int64_t nstats,
+                                                      const HjStepArgs A, double *__restrict__ state, int mode)
+{
+    __shared__ double red[4][256];
+    const int tid = threadIdx.x;
+    double m = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t i = tid; i < nparts; i += 256) m = fmax(m, part[i]);
+    for (int64_t i = tid; i < nstats; i += 256) {
+        s0 += stats[3 * i + 0];
+        s1 += stats[3 * i + 1];
+        s2 += stats[3 * i + 2];
+    }
+    red[0][tid] = m;
+    red[1][tid] = s0;
+    red[2][tid] = s1;
+    red[3][tid] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[0][tid] = fmax(red[0][tid], red[0][tid + s]);
+            red[1][tid] += red[1][tid + s];
+            red[2][tid] += red[2][tid + s];
+            red[3][tid] += red[3][tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (mode == 0) {
+            state[HJ_S_C] = red[0][0];
+            state[HJ_S_T] = 0.0;
+            state[HJ_S_STEPS] = 0.0;
+            state[HJ_S_FALLBACK] = 0.0;
+            state[HJ_S_ERRSUM] = 0.0;
+            state[HJ_S_JUDGED] = 0.0;
+        } else {
+            // steps past t_end (dt = 0) leave u and the state unchanged
+            const double dt = hj_dt(A, state);
+            if (dt > 0.0) {
+                state[HJ_S_T] += dt;
+                state[HJ_S_STEPS] += 1.0;
+                state[HJ_S_C] = red[0][0];
+                state[HJ_S_FALLBACK] += red[1][0];
+                state[HJ_S_ERRSUM] += red[2][0];
+                state[HJ_S_JUDGED] += red[3][0];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Training samples: features and WENO-Z weights of the stencils of a field along one axis
+// (both sides of every point: rows 2p (J_R) and 2p + 1 (J_L)).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) hj_harvest(const double *__restrict__ u, const HjQuadArgs A,
+                                                  float *__restrict__ X, float *__restrict__ Y)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= A.nx * A.ny) return;
+    const int64_t pj = p / A.nx, pi = p % A.nx;
+    double v[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        int64_t idx;
+        if (A.axis == 0) {
+            int64_t i2 = pi + (k - 3);
+            i2 = i2 < 0 ? i2 + A.nx : (i2 >= A.nx ? i2 - A.nx : i2);
+            idx = pj * A.nx + i2;
+        } else {
+            int64_t j2 = pj + (k - 3);
+            j2 = j2 < 0 ? j2 + A.ny : (j2 >= A.ny ? j2 - A.ny : j2);
+            idx = j2 * A.nx + pi;
+        }
+        v[k] = u[idx];
+    }
+    for (int side = 0; side < 2; ++side) {
+        double s[5], om[3];
+        float f[MLP_IN];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s[k] = side == 0 ? v[k] : v[6 - k];
+        stencil_features(s, f);
+        wenoz(s, A.d, om);
+        const int64_t row = 2 * p + side;
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) X[row * MLP_IN + k] = f[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Y[row * 3 + r] = (float)om[r];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Proposer inference and training.  Blocks of 256 threads, each wave a tile of 16 samples per
+// step (samples beyond n are zero features and carry no loss).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) mlp_forward(const float *__restrict__ P, const float *__restrict__ X,
+                                                   float *__restrict__ Y, int64_t n)
+{
+    __shared__ float feat[4][16][MLP_IN];
+    __shared__ float hid[4][16][33];
+    __shared__ float zo[4][16][4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const MlpOperands o = mlp_load(P, lane);
+    auto bar = [] { __syncthreads(); };
+    const int64_t ntiles = (n + 15) / 16;
+    const int64_t per_block = 4;
+    for (int64_t t0 = (int64_t)blockIdx.x * per_block; t0 < ntiles; t0 += (int64_t)gridDim.x * per_block) {
+        const int64_t tile = t0 + wv;
+        // features of this wave's tile
+        for (int e = lane; e < 16 * MLP_IN; e += 64) {
+            const int64_t row = tile * 16 + e / MLP_IN;
+            feat[wv][e / MLP_IN][e % MLP_IN] = (tile < ntiles && row < n) ? X[row * MLP_IN + e % MLP_IN] : 0.f;
+        }
+        __syncthreads();
+        mlp_tile_forward(o, feat[wv], hid[wv], zo[wv], (float(*)[16][33]) nullptr, lane, bar);
+        if (lane < 16) {
+            const int64_t row = tile * 16 + lane;
+            if (tile < ntiles && row < n) {
+                double om[3];
+                softmax3(zo[wv][lane], om);
+                Y[row * 3 + 0] = (float)om[0];
+                Y[row * 3 + 1] = (float)om[1];
+                Y[row * 3 + 2] = (float)om[2];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Fused forward + backward of the loss mean_i sum_r (omega_ir - target_ir)^2 over a batch; each wave
+// accumulates its gradient contributions and writes them to its slot of `partial` (MLP_NPARAM
+// floats per wave) plus its summed squared error at partial[slot * MLP_NPARAM + MLP_NPARAM - 1 + 1]
+// -- the slot holds MLP_NPARAM + 1 floats.
+__global__ void __launch_bounds__(256) mlp_train_tile(const float *__restrict__ P, const float *__restrict__ X,
+                                                      const float *__restrict__ Yt, int64_t n,
+                                                      float *__restrict__ partial)
+{
+    __shared__ float feat[4][16][MLP_IN];
+    __shared__ float hid[4][16][33];
+    __shared__ float zo[4][16][4];
+    __shared__ float keep[4][4][16][33];  // z1, h1 (bf16-valued), z2, h2 per wave
+    __shared__ float gz[4][16][33];       // upstream gradient of the layer being processed
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const MlpOperands o = mlp_load(P, lane);
+    auto bar = [] { __syncthreads(); };
+    // gradient accumulators in MFMA result layout
+    f32x4 gW3[2] = {};     // D[out 4g+j][unit 16t+m]  (M = out padded to 16, N = 32)
+    f32x4 gW2[2][2] = {};  // [M-tile a][N-tile t]: D[unit 16a+4g+j][unit 16t+m]
+    f32x4 gW1[2] = {};     // [M-tile a]: D[unit 16a+4g+j][feature m]
+    float gb1[2] = {0.f, 0.f}, gb2[2] = {0.f, 0.f}, gb3 = 0.f, sq = 0.f;
+    const int64_t ntiles = (n + 15) / 16;
+    const float inv_n = 1.0f / (float)n;
+    for (int64_t t0 = (int64_t)blockIdx.x * 4; t0 < ntiles; t0 += (int64_t)gridDim.x * 4) {
+        const int64_t tile = t0 + wv;
+        const bool tile_ok = tile < ntiles;
+        for (int e = lane; e < 16 * MLP_IN; e += 64) {
+            const int64_t row = tile * 16 + e / MLP_IN;
+            feat[wv][e / MLP_IN][e % MLP_IN] = (tile_ok && row < n) ? X[row * MLP_IN + e % MLP_IN] : 0.f;
+        }
+        __syncthreads();
+        mlp_tile_forward(o, feat[wv], hid[wv], zo[wv], keep[wv], lane, bar);
+        // keep[1] = bf16(relu(z1)), keep[3] = bf16(relu(z2)): the operands the forward used
+        for (int e = lane; e < 16 * 32; e += 64) {
+            const int r = e >> 5, c = e & 31;
+            const short h1 = f2bf(fmaxf(keep[wv][0][r][c], 0.f));
+            const short h2 = f2bf(fmaxf(keep[wv][2][r][c], 0.f));
+            keep[wv][1][r][c] = __uint_as_float((uint32_t)(uint16_t)h1 << 16);
+            keep[wv][3][r][c] = __uint_as_float((uint32_t)(uint16_t)h2 << 16);
+        }
+        // output gradient: softmax Jacobian of 2 (om - y) / n
+        if (lane < 16) {
+            const int64_t row = tile * 16 + lane;
+            float g3[3] = {0.f, 0.f, 0.f};
+            if (tile_ok && row < n) {
+                double om[3];
+                softmax3(zo[wv][lane], om);
+                double go[3], dot = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    const double e = om[r] - (double)Yt[row * 3 + r];
+                    sq += (float)(e * e);
+                    go[r] = 2.0 * e * (double)inv_n;
+                    dot += go[r] * om[r];
+                }
+                for (int r = 0; r < 3; ++r) g3[r] = (float)(om[r] * (go[r] - dot));
+            }
+            for (int c = 0; c < 16; ++c) gz[wv][lane][c] = c < 3 ? g3[c] : 0.f;
+        }
+        __syncthreads();
+        // dW3 += G3^T H2: A[out][sample] = G3[sample][out], B[sample][unit] = H2[sample][unit]
+        {
+            bf16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = f2bf(gz[wv][4 * g + j][m]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                bf16x4 b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = f2bf(keep[wv][3][4 * g + j][16 * t + m]);
+                gW3[t] = mfma16(a, b, gW3[t]);
+            }
+        }
+        if (lane < MLP_OUT)
+            for (int r = 0; r < 16; ++r) gb3 += gz[wv][r][lane];
+        // dH2 = G3 W3: A[sample][out] = G3, B[out][unit] = W3[out][unit] (rows >= 3 zero)
+        f32x4 dh2[2];
+        {
+            bf16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = f2bf(gz[wv][m][4 * g + j]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                bf16x4 b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 4 * g + j;
+                    b[j] = k < MLP_OUT ? f2bf(P[MLP_W3 + k * MLP_H + 16 * t + m]) : (short)0;
+                }
+                const f32x4 zc = {0.f, 0.f, 0.f, 0.f};
+                dh2[t] = mfma16(a, b, zc);
+            }
+        }
+        __syncthreads();
+        // G2 = dH2 * (z2 > 0) -> gz
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * g + j, c = 16 * t + m;
+                gz[wv][r][c] = keep[wv][2][r][c] > 0.f ? dh2[t][j] : 0.f;
+            }
+        __syncthreads();
+        for (int t = 0; t < 2; ++t)
+            if (lane < 16)
+                for (int r = 0; r < 16; ++r) gb2[t] += gz[wv][r][16 * t + lane];
+        // dW2 += G2^T H1: A[unit a][sample] = G2[sample][unit], B[sample][unit'] = H1
+        {
+#pragma unroll
+            for (int a_ = 0; a_ < 2; ++a_) {
+                bf16x4 a;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = f2bf(gz[wv][4 * g + j][16 * a_ + m]);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    bf16x4 b;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) b[j] = f2bf(keep[wv][1][4 * g + j][16 * t + m]);
+                    gW2[a_][t] = mfma16(a, b, gW2[a_][t]);
+                }
+            }
+        }
+        // dH1 = G2 W2: A[sample][unit k] = G2, B[k][unit n] = W2[k][n]
+        f32x4 dh1[2];
+        {
+            bf16x4 a[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[s][j] = f2bf(gz[wv][m][16 * s + 4 * g + j]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    bf16x4 b;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) b[j] = f2bf(P[MLP_W2 + (16 * s + 4 * g + j) * MLP_H + 16 * t + m]);
+                    acc = mfma16(a[s], b, acc);
+                }
+                dh1[t] = acc;
+            }
+        }
+        __syncthreads();
+        // G1 = dH1 * (z1 > 0) -> gz
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * g + j, c = 16 * t + m;
+                gz[wv][r][c] = keep[wv][0][r][c] > 0.f ? dh1[t][j] : 0.f;
+            }
+        __syncthreads();
+        for (int t = 0; t < 2; ++t)
+            if (lane < 16)
+                for (int r = 0; r < 16; ++r) gb1[t] += gz[wv][r][16 * t + lane];
+        // dW1 += G1^T X: A[unit][sample] = G1[sample][unit], B[sample][feature] = X (features < 8)
+#pragma unroll
+        for (int a_ = 0; a_ < 2; ++a_) {
+            bf16x4 a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a[j] = f2bf(gz[wv][4 * g + j][16 * a_ + m]);
+                b[j] = m < MLP_IN ? f2bf(feat[wv][4 * g + j][m]) : (short)0;
+            }
+            gW1[a_] = mfma16(a, b, gW1[a_]);
+        }
+        __syncthreads();
+    }
+    // write this wave's partial gradient (slot = global wave index)
+    float *dst = partial + ((int64_t)blockIdx.x * 4 + wv) * (MLP_NPARAM + 1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int out = 4 * g + j;
+            if (out < MLP_OUT) dst[MLP_W3 + out * MLP_H + 16 * t + m] = gW3[t][j];
+        }
+#pragma unroll
+    for (int a_ = 0; a_ < 2; ++a_)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[MLP_W2 + (16 * a_ + 4 * g + j) * MLP_H + 16 * t + m] = gW2[a_][t][j];
+#pragma unroll
+    for (int a_ = 0; a_ < 2; ++a_)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (m < MLP_IN) dst[MLP_W1 + (16 * a_ + 4 * g + j) * MLP_IN + m] = gW1[a_][j];
+    if (lane < 16) {
+        dst[MLP_B1 + lane] = gb1[0];
+        dst[MLP_B1 + 16 + lane] = gb1[1];
+        dst[MLP_B2 + lane] = gb2[0];
+        dst[MLP_B2 + 16 + lane] = gb2[1];
+    }
+    if (lane < MLP_OUT) dst[MLP_B3 + lane] = gb3;
+    // squared error of this wave's samples (lanes 0..15 hold them)
+    __shared__ float sqs[256];
+    sqs[tid] = sq;
+    __syncthreads();
+    if (lane == 0) {
+        float s = 0.f;
+        for (int k = 0; k < 16; ++k) s += sqs[wv * 64 + k];
+        dst[MLP_NPARAM] = s;
+    }
+}
+
+// grad[k] = sum over slots of partial[slot][k] (k < MLP_NPARAM); loss = sum of the squared errors / n
+__global__ void __launch_bounds__(256) mlp_reduce_grads(const float *__restrict__ partial, int64_t nslots, int64_t n,
+                                                        float *__restrict__ grad, float *__restrict__ loss)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k > MLP_NPARAM) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < nslots; ++i) s += (double)partial[i * (MLP_NPARAM + 1) + k];
+    if (k < MLP_NPARAM)
+        grad[k] = (float)s;
+    else
+        loss[0] = (float)(s / (double)n);
+}
+
+// Adam (Kingma & Ba) on the FP32 master parameters; t = step number (>= 1).
+__global__ void __launch_bounds__(256) mlp_adam(float *__restrict__ P, const float *__restrict__ grad,
+                                                float *__restrict__ M, float *__restrict__ V, int t, float lr,
+                                                float b1, float b2, float eps)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= MLP_NPARAM) return;
+    const float gk = grad[k];
+    const float mk = b1 * M[k] + (1.f - b1) * gk;
+    const float vk = b2 * V[k] + (1.f - b2) * gk * gk;
+    M[k] = mk;
+    V[k] = vk;
+    const float mh = mk / (1.f - powf(b1, (float)t));
+    const float vh = vk / (1.f - powf(b2, (float)t));
+    P[k] = P[k] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+hipError_t launch_hj_weno_quad(int mode, const double *u, double *JL, double *JR, const HjQuadArgs &A,
+                               const float *P, double *stats, hipStream_t st)
+{
+    const int64_t npts = A.nx * A.ny;
+    const dim3 grid((unsigned)((npts + 255) / 256));
+    if (mode == HJ_LINEAR)
+        hipLaunchKernelGGL(hj_weno_quad<HJ_LINEAR>, grid, dim3(256), 0, st, u, JL, JR, A, P, stats);
+    else if (mode == HJ_WENOZ)
+        hipLaunchKernelGGL(hj_weno_quad<HJ_WENOZ>, grid, dim3(256), 0, st, u, JL, JR, A, P, stats);
+    else
+        hipLaunchKernelGGL(hj_weno_quad<HJ_LEARNED>, grid, dim3(256), 0, st, u, JL, JR, A, P, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_hj_update(double *u, const double *DmX, const double *DpX, const double *DmY, const double *DpY,
+                            const HjStepArgs &A, const double *state, double *part, hipStream_t st)
+{
+    const dim3 grid((unsigned)((A.npts + 255) / 256));
+    hipLaunchKernelGGL(hj_update, grid, dim3(256), 0, st, u, DmX, DpX, DmY, DpY, A, state, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_hj_init_speed(const double *u, const HjStepArgs &A, double *part, hipStream_t st)
+{
+    const dim3 grid((unsigned)((A.npts + 255) / 256));
+    hipLaunchKernelGGL(hj_init_speed, grid, dim3(256), 0, st, u, A, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_hj_finish(const double *part, int64_t nparts, const double *stats, int64_t nstats,
+                            const HjStepArgs &A, double *state, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(hj_finish_step, dim3(1), dim3(256), 0, st, part, nparts, stats, nstats, A, state, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_hj_harvest(const double *u, const HjQuadArgs &A, float *X, float *Y, hipStream_t st)
+{
+    const int64_t npts = A.nx * A.ny;
+    hipLaunchKernelGGL(hj_harvest, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, u, A, X, Y);
+    return hipGetLastError();
+}
+
+int64_t mlp_train_slots(int64_t n)
+{
+    const int64_t ntiles = (n + 15) / 16;
+    int64_t blocks = (ntiles + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
+    return blocks * 4;
+}
+
+hipError_t launch_mlp_forward(const float *P, const float *X, float *Y, int64_t n, hipStream_t st)
+{
+    const int64_t ntiles = (n + 15) / 16;
+    int64_t blocks = (ntiles + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(mlp_forward, dim3((unsigned)blocks), dim3(256), 0, st, P, X, Y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *Y, int64_t n, float *partial, float *grad,
+                           float *loss, hipStream_t st)
+{
+    const int64_t slots = mlp_train_slots(n);
+    hipLaunchKernelGGL(mlp_train_tile, dim3((unsigned)(slots / 4)), dim3(256), 0, st, P, X, Y, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mlp_reduce_grads, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, partial, slots, n, grad,
+                       loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *P, const float *grad, float *M, float *V, int t, float lr, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, P, grad, M, V, t, lr, 0.9f, 0.999f,
+                       1e-8f);
+    return hipGetLastError();
+}
+
+}  // namespace scx

@@ -67,6 +67,7 @@ struct OpSpec {
     int op;
     double alpha, scale;
     int k;
+    int identity = 0;  // 1: the operand already holds the local integrals (J_R for L_R, J_L for L_L)
 };
 
 sc_status check_grid(const sc_grid *g);
@@ -75,7 +76,8 @@ size_t elem_bytes(const sc_grid *g);
 size_t round256(size_t b);
 bool overlap(const void *a, const void *b, size_t bytes);
 int pick_variant(bool contig, int64_t n, int elem);
-void fill_op(OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid, double scale, int k);
+void fill_op(OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid, double scale, int k,
+             int identity = 0);
 void fill_ext(PassArgs *a, int order);
 size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops);
 int64_t nchunks_for(const Axis &ax, int elem);

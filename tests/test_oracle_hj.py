@@ -171,12 +171,18 @@ def test_features_are_shift_and_scale_invariant_except_the_scale_feature():
     S = r.standard_normal((20, 5))
     f = mlp.features(S)
     g = mlp.features(3.0 * S + 7.0)
-    assert np.allclose(f[:, :5], g[:, :5], atol=1e-14)
-    unclipped = (np.abs(f[:, 5]) < 0.99) & (np.abs(g[:, 5]) < 0.99)
+    inv = [0, 1, 2, 4, 5, 6, 7]
+    assert np.allclose(f[:, inv], g[:, inv], atol=1e-14)
+    unclipped = (np.abs(f[:, 3]) < 0.99) & (np.abs(g[:, 3]) < 0.99)
     assert unclipped.any()
-    assert np.allclose((g[:, 5] - f[:, 5])[unclipped], math.log10(9.0) / 8, atol=1e-12)
-    assert (np.abs(f[:, :5]) <= 1 + 1e-15).all() and np.all(f[:, 6:] == 0)
-    assert np.all(mlp.features(np.ones((1, 5)))[:, :5] == 0)
+    assert np.allclose((g[:, 3] - f[:, 3])[unclipped], math.log10(9.0) / 8, atol=1e-12)
+    assert (np.abs(f) <= 1 + 1e-15).all()
+    # second differences: a quadratic stencil has q_0 = q_1 = q_2
+    eta = np.array(hj.ETA5, dtype=float)
+    fq = mlp.features((0.4 * eta ** 2 - eta)[None, :])
+    assert np.allclose(fq[0, :3], np.sign(0.8) * np.ones(3))
+    c = mlp.features(np.ones((1, 5)))
+    assert np.all(c[:, [0, 1, 2, 4, 5, 6, 7]] == 0) and c[0, 3] == -1.0
 
 
 def test_mlp_gradients_match_central_differences():
