@@ -203,3 +203,45 @@ def time_step(grid: _Grid, c, nu_diff, beta, dt, order, nsteps, u, split=False):
     _check(_load().sco_time_step(ctypes.byref(grid), ctypes.byref(p), nsteps, _p(u)),
            "time_step")
     return u
+
+
+def _euler_partial_sums(grid: _Grid, c, nu_diff, beta, dt, order, u, k):
+    """u + dt F(u), F the right-hand side of u_t + c.grad u = nu lap u with every D replaced by the
+    partial sum S_k = sum_{p=1..k} D^p (Sec. 2.5): -|c_d| dt alpha S_k(D_{R/L}) - nu dt alpha^2 S_k(D_0)."""
+    import math
+
+    out = u.copy()
+    for dim in range(grid.ndim):
+        cd = c[dim] if dim < len(c) else 0.0
+        if cd != 0.0:
+            a = beta / (abs(cd) * dt)
+            out += -abs(cd) * dt * a * apply_D_partial_sum(grid, dim, "R" if cd > 0 else "L", order, a, k, 1.0, u)
+        if nu_diff > 0.0:
+            a = beta / math.sqrt(nu_diff * dt)
+            out += -nu_diff * dt * a * a * apply_D_partial_sum(grid, dim, "0", order, a, k, 1.0, u)
+    return out
+
+
+def time_step_rk(grid: _Grid, c, nu_diff, beta, dt, order, nsteps, u, stages):
+    """s-stage explicit Runge-Kutta (Sec. 2.5) coupled to partial sums of the same order s, in the
+    strong-stability-preserving Shu-Osher forms (s = 1: forward Euler; s = 2: u1 = E(u),
+    u <- u/2 + E(u1)/2; s = 3: u1 = E(u), u2 = 3u/4 + E(u1)/4, u <- u/3 + 2 E(u2)/3), E the Euler
+    step with S_s.  Periodic axes only (partial sums beyond k = 1 need periodic lines)."""
+    u = _f64(u).copy()
+
+    def E(v):
+        return _euler_partial_sums(grid, c, nu_diff, beta, dt, order, v, stages)
+
+    for _ in range(nsteps):
+        if stages == 1:
+            u = E(u)
+        elif stages == 2:
+            u1 = E(u)
+            u = 0.5 * u + 0.5 * E(u1)
+        elif stages == 3:
+            u1 = E(u)
+            u2 = 0.75 * u + 0.25 * E(u1)
+            u = u / 3.0 + (2.0 / 3.0) * E(u2)
+        else:
+            raise ValueError("stages must be 1, 2 or 3")
+    return u

@@ -193,3 +193,86 @@ def test_symbol_error_matches_oracle_run_on_small_grid():
     S = _step_symbol((1, 0), (dx, dx), (0, 0), 1.0, 1.0, dx, 6)
     ref = np.real(S ** 4) * (np.sin(X) + np.sin(Y))
     np.testing.assert_allclose(u, ref, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------------------ Runge-Kutta stages
+def _stage_z(kvec, dxs, c, nu_diff, beta, dt, order, s):
+    """z of one Euler step with every D replaced by S_s: the symbol of D is 1 - s_hat, of S_s the
+    geometric sum sum_{p=1..s} (1 - s_hat)^p."""
+    z = 0j
+    for d, (k, dx) in enumerate(zip(kvec, dxs)):
+        th = k * dx
+        if c[d] != 0:
+            a = beta / (abs(c[d]) * dt)
+            D = 1 - _sym("R" if c[d] > 0 else "L", a * dx, order, th)
+            z -= abs(c[d]) * dt * a * sum(D ** p for p in range(1, s + 1))
+        if nu_diff > 0:
+            a = beta / math.sqrt(nu_diff * dt)
+            D = 1 - _sym("0", a * dx, order, th)
+            z -= nu_diff * dt * a * a * sum(D ** p for p in range(1, s + 1))
+    return z
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3])
+def test_runge_kutta_step_amplifies_each_mode_by_the_stability_polynomial(stages):
+    """For a linear periodic problem every SSP form of s stages multiplies a mode by the Taylor
+    polynomial sum_{j<=s} z^j / j! of its Euler increment z."""
+    n = (40, 36)
+    L = (2 * np.pi, 2 * np.pi)
+    dxs = [L[d] / n[d] for d in range(2)]
+    X, Y = np.meshgrid(np.arange(n[0]) * dxs[0], np.arange(n[1]) * dxs[1])
+    modes = [((2, 1), 0.6, 0.4), ((-5, 3), 0.3, 1.7), ((7, -6), 0.2, 0.1)]
+    c, nu_diff, beta, dt, steps = (1.0, -0.6), 0.4, 1.0, 0.05, 3
+    u0 = sum(a * np.cos(k[0] * X + k[1] * Y + ph) for k, a, ph in modes)
+    g = oracle.make_grid(n, (0, 0), L)
+    got = oracle.time_step_rk(g, c, nu_diff, beta, dt, 6, steps, u0, stages)
+    ref = 0.0
+    for k, a, ph in modes:
+        z = _stage_z(k, dxs, c, nu_diff, beta, dt, 6, stages)
+        R = sum(z ** j / math.factorial(j) for j in range(stages + 1))
+        ref = ref + np.real(a * np.exp(1j * ph) * R ** steps * np.exp(1j * (k[0] * X + k[1] * Y)))
+    # rounding: D = v - L^{-1} v cancels by up to (alpha dx / theta)^2 and enters up to the power s
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11)
+    if stages == 1:
+        np.testing.assert_allclose(got, oracle.time_step(g, c, nu_diff, beta, dt, 6, steps, u0), atol=1e-14)
+
+
+@pytest.mark.parametrize("stages,example", [(1, "advection"), (2, "advection"), (3, "advection"),
+                                            (1, "diffusion"), (2, "diffusion"), (3, "diffusion")])
+def test_runge_kutta_with_partial_sums_converges_at_order_s(stages, example):
+    """Examples 1 and 2 (Sec. 5.1): u_t + u_x + u_y = 0 and u_t = u_xx + u_yy on [0, 2 pi]^2 with smooth
+    periodic solutions, on a fixed 48^2 grid (sixth-order quadrature: spatial error negligible) and
+    dt = T/M refined: the error falls like dt^s.  beta within each form's stability bound: a 2-D
+    diffusion increment reaches z = -2 s beta^2, which the s-stage form tolerates down to -2
+    (s <= 2) or -2.51 (s = 3), so beta = 0.6; advection runs at beta = 1 (0.9 for s = 3)."""
+    N = 48
+    dx = 2 * np.pi / N
+    x = np.arange(N) * dx
+    X, Y = np.meshgrid(x, x)
+    g = oracle.make_grid((N, N), (0, 0), (2 * np.pi, 2 * np.pi))
+    errs = []
+    for M in (8, 16, 32):
+        if example == "advection":
+            T, beta = 1.0, (0.9 if stages == 3 else 1.0)
+            u = oracle.time_step_rk(g, (1.0, 1.0), 0.0, beta, T / M, 6, M, np.sin(X + Y), stages)
+            exact = np.sin(X + Y - 2 * T)
+        else:
+            T, beta = 0.25, 0.6
+            u = oracle.time_step_rk(g, (0.0, 0.0), 1.0, beta, T / M, 6, M, np.sin(X) * np.sin(Y), stages)
+            exact = np.exp(-2 * T) * np.sin(X) * np.sin(Y)
+        errs.append(np.abs(u - exact).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > stages - 0.3, (errs, rates)
+
+
+def test_stage_forms_are_unstable_beyond_their_beta_bound():
+    """The bound above is sharp for the grid-scale 2-D diffusion mode where nu = alpha dx is about 1
+    (48^2, dt = 1/64: |D_0| ~ 0.92 there): RK3 with S_3 at beta = 0.9 amplifies it, beta = 0.6 does not."""
+    N = 48
+    dx = 2 * np.pi / N
+    worst = {}
+    for beta in (0.6, 0.9):
+        worst[beta] = max(abs(sum(_stage_z((kx, ky), (dx, dx), (0.0, 0.0), 1.0, beta, 0.25 / 16, 6, 3) ** j
+                                  / math.factorial(j) for j in range(4)))
+                          for kx in range(N // 2 + 1) for ky in range(N // 2 + 1))
+    assert worst[0.9] > 1.5 and worst[0.6] <= 1.0 + 1e-12, worst
