@@ -109,7 +109,14 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int ord
  * axis in turn, x then y then z, each acting on the previous one's result (per-axis factors of
  * modulus <= 1 at beta = 1).  Dirichlet axes hold u = 0 at both ends.  nn_policy applies the nearest-neighbour time-step bound
  * of Sec. 3.1 with tolerance nn_eps over blocks of length block_len (0 = the whole axis):
- * 0 = ignore, 1 = reduce dt to the bound, 2 = fail with SC_ERR_ARG if dt exceeds it. */
+ * 0 = ignore, 1 = reduce dt to the bound, 2 = fail with SC_ERR_ARG if dt exceeds it.
+ * stages = s in {2, 3} (Sec. 2.5): an s-stage explicit Runge-Kutta method coupled to partial sums of
+ * the same order -- every D above replaced by S_s = sum_{p=1..s} D^p -- in the strong-stability-
+ * preserving Shu-Osher forms (E = the additive Euler step with S_s; s = 2: u1 = E(u), u <- u/2 +
+ * E(u1)/2; s = 3: u1 = E(u), u2 = 3u/4 + E(u1)/4, u <- u/3 + 2E(u2)/3); O(dt^s).  Unsplit, periodic
+ * axes only (SC_ERR_UNSUPPORTED otherwise).  Stability needs beta small enough that the Euler
+ * increment of every mode stays in the method's region: a d-dimensional diffusion increment reaches
+ * -d s beta^2 (s = 2: >= -2; s = 3: >= -2.51). */
 typedef struct {
     double c[3];
     double nu_diff;
@@ -120,14 +127,14 @@ typedef struct {
     double nn_eps;    /* 0 -> 1e-16 */
     double block_len; /* 0 -> axis length */
     int32_t split;    /* 0 additive (unsplit), 1 dimension-split x, y, z */
-    int32_t reserved; /* must be 0 */
+    int32_t stages;   /* 0 or 1: the Euler step above; 2, 3: s-stage SSP Runge-Kutta (see below) */
 } sc_linear_pde;
 
 sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps, void *u,
                        void *ws, size_t ws_bytes, sc_stream_t stream);
 
 /* Workspace bytes needed by one call: which = 0 sc_apply_invL, 1 sc_apply_D_partial_sum (for k),
- * 2 sc_time_step.  Returns 0 on invalid arguments. */
+ * 2 sc_time_step (k = the number of stages; 1 for the Euler step).  Returns 0 on invalid arguments. */
 size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k);
 
 /* The time step actually used by sc_time_step for this pde (after the nearest-neighbour policy),

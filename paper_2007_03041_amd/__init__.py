@@ -50,7 +50,7 @@ class sc_grid(ctypes.Structure):
 class sc_linear_pde(ctypes.Structure):
     _fields_ = [("c", c_double * 3), ("nu_diff", c_double), ("beta", c_double), ("dt", c_double),
                 ("order", c_int32), ("nn_policy", c_int32), ("nn_eps", c_double),
-                ("block_len", c_double), ("split", c_int32), ("reserved", c_int32)]
+                ("block_len", c_double), ("split", c_int32), ("stages", c_int32)]
 
 
 class sc_batch_item(ctypes.Structure):
@@ -284,13 +284,13 @@ def apply_D_partial_sum(v, grid: Grid, dim: int, op: str, order: int, alpha: flo
 
 
 def make_pde(c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6, nn_policy=0, nn_eps=0.0,
-             block_len=0.0, split=False) -> sc_linear_pde:
+             block_len=0.0, split=False, stages=1) -> sc_linear_pde:
     p = sc_linear_pde()
     for e in range(3):
         p.c[e] = float(c[e]) if e < len(c) else 0.0
     p.nu_diff, p.beta, p.dt, p.order = float(nu_diff), float(beta), float(dt), int(order)
     p.nn_policy, p.nn_eps, p.block_len = int(nn_policy), float(nn_eps), float(block_len)
-    p.split, p.reserved = int(bool(split)), 0
+    p.split, p.stages = int(bool(split)), int(stages)
     return p
 
 
@@ -300,7 +300,7 @@ class TimeStepper:
     def __init__(self, grid: Grid, pde: sc_linear_pde, device="cuda"):
         self.grid, self.pde = grid, pde
         self._gc = grid.c()
-        nbytes = int(load().sc_workspace_bytes(ctypes.byref(self._gc), 0, 2, 1))
+        nbytes = int(load().sc_workspace_bytes(ctypes.byref(self._gc), 0, 2, max(1, int(pde.stages))))
         self._ws, self._wsp = _workspace(nbytes, device)
         self._nbytes = nbytes
 
@@ -312,9 +312,10 @@ class TimeStepper:
 
 
 def time_step(u, grid: Grid, nsteps: int, c=(0.0, 0.0, 0.0), nu_diff=0.0, beta=1.0, dt=1e-3, order=6,
-              nn_policy=0, nn_eps=0.0, block_len=0.0, split=False):
-    """Advance u (in place) by ``nsteps`` first-order steps of u_t + c.grad u = nu_diff lap u."""
-    pde = make_pde(c, nu_diff, beta, dt, order, nn_policy, nn_eps, block_len, split)
+              nn_policy=0, nn_eps=0.0, block_len=0.0, split=False, stages=1):
+    """Advance u (in place) by ``nsteps`` steps of u_t + c.grad u = nu_diff lap u: forward Euler with D
+    (stages 1) or the s-stage Runge-Kutta form with partial sums S_s (stages 2, 3)."""
+    pde = make_pde(c, nu_diff, beta, dt, order, nn_policy, nn_eps, block_len, split, stages)
     return TimeStepper(grid, pde, u.device).step(u, nsteps)
 
 

@@ -365,6 +365,12 @@ size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k)
     if (check_grid(grid) != SC_OK) return 0;
     if (which == 2) {
         size_t b = round256((size_t)axis_of(grid, 0).total * elem_bytes(grid));
+        if (k >= 2) {
+            // Runge-Kutta stages: stage, Euler result and partial-sum fields, then the partial sums' own
+            size_t ps = 0;
+            for (int d = 0; d < grid->ndim; ++d) ps = std::max(ps, sc_workspace_bytes(grid, d, 1, k));
+            return 3 * b + ps + 256;
+        }
         size_t extra = 0;
         for (int d = 0; d < grid->ndim; ++d) {
             const Axis ax = axis_of(grid, d);
@@ -457,6 +463,13 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
         return fail(SC_ERR_ARG, "dt and beta must be > 0 and nu_diff >= 0");
     if (pde->nn_policy < 0 || pde->nn_policy > 2) return fail(SC_ERR_ARG, "nn_policy must be 0, 1 or 2");
     if (pde->split != 0 && pde->split != 1) return fail(SC_ERR_ARG, "split must be 0 or 1");
+    if (pde->stages < 0 || pde->stages > 3) return fail(SC_ERR_ARG, "stages must be 0..3");
+    const int stages = pde->stages < 1 ? 1 : pde->stages;
+    if (stages > 1) {
+        if (pde->split) return fail(SC_ERR_UNSUPPORTED, "Runge-Kutta stages use the unsplit form");
+        for (int d = 0; d < grid->ndim; ++d)
+            if (grid->bc[d] != SC_BC_PERIODIC) return fail(SC_ERR_UNSUPPORTED, "Runge-Kutta stages need periodic axes");
+    }
     double dt = pde->dt;
     if (pde->nn_policy != 0) {
         const double bound = nn_bound(grid, pde);
@@ -467,7 +480,7 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
     }
     for (int d = 0; d < grid->ndim; ++d)
         if (grid->n[d] < pde->order + 1) return fail(SC_ERR_SHAPE, "line shorter than the stencil");
-    const size_t need = sc_workspace_bytes(grid, 0, 2, 1);
+    const size_t need = sc_workspace_bytes(grid, 0, 2, stages) - 256;
     if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small (see sc_workspace_bytes)");
     if ((uintptr_t)ws & 255) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
     const Axis ax0 = axis_of(grid, 0);
@@ -495,6 +508,42 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
             const double nu = ops[d][o].alpha * axis_of(grid, d).dx;
             if (!(nu < 700.0) || !std::isfinite(nu)) return fail(SC_ERR_ARG, "alpha * dx too large (> 700)");
         }
+    }
+    if (stages > 1) {
+        // s-stage SSP Runge-Kutta with every D replaced by S_s (Sec. 2.5); E(v) = v + sum scale S_s[v]
+        const int elem = (int)elem_bytes(grid);
+        const int64_t nel = ax0.total;
+        char *U1 = wsp, *B = wsp + round256(fbytes), *TMP = B + round256(fbytes);
+        char *psw = TMP + round256(fbytes);
+        const size_t psw_bytes = ws_bytes - 3 * round256(fbytes);
+        auto lin = [&](double a, const void *x, double b, const void *y, void *o) {
+            return timed("lincomb", st, [&](const char **) { return scx::launch_lincomb(nel, elem, a, x, b, y, o, st); });
+        };
+        auto euler = [&](const void *v, void *o) -> sc_status {
+            if (lin(1.0, v, 0.0, v, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+            for (int d = 0; d < grid->ndim; ++d)
+                for (int k = 0; k < nops[d]; ++k) {
+                    sc_status r = sc_apply_D_partial_sum(grid, d, (sc_op)ops[d][k].op, pde->order, ops[d][k].alpha, stages,
+                                                         ops[d][k].scale, nullptr, v, TMP, psw, psw_bytes, stream);
+                    if (r != SC_OK) return r;
+                    if (lin(1.0, o, 1.0, TMP, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+                }
+            return SC_OK;
+        };
+        for (int step = 0; step < nsteps; ++step) {
+            s = euler(u, U1);
+            if (s == SC_OK) s = euler(U1, B);
+            if (s != SC_OK) return s;
+            if (stages == 2) {
+                if (lin(0.5, u, 0.5, B, u) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+                continue;
+            }
+            if (lin(0.75, u, 0.25, B, U1) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+            s = euler(U1, B);
+            if (s != SC_OK) return s;
+            if (lin(1.0 / 3.0, u, 2.0 / 3.0, B, u) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+        }
+        return SC_OK;
     }
     for (int step = 0; step < nsteps; ++step) {
         bool first = true;

@@ -172,6 +172,14 @@ __global__ void __launch_bounds__(256) sweep_kernel(const PassArgs a, const T *J
     }
 }
 
+// out = a x + b y (element-wise; out may be x or y)
+template <typename T>
+__global__ void __launch_bounds__(256) lincomb_kernel(int64_t nel, double a, const T *x, double b, const T *y, T *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nel) out[i] = (T)fma(a, (double)x[i], b * (double)y[i]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) axpy_kernel(int64_t nel, double s, const T *x, T *y, int init)
 {
@@ -284,6 +292,19 @@ hipError_t launch_axpy(int64_t nel, int elem, double s, const void *x, void *y, 
         hipLaunchKernelGGL((axpy_kernel<double>), grid, dim3(256), 0, st, nel, s, (const double *)x, (double *)y, init);
     else
         hipLaunchKernelGGL((axpy_kernel<float>), grid, dim3(256), 0, st, nel, s, (const float *)x, (float *)y, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(int64_t nel, int elem, double a, const void *x, double b, const void *y, void *out,
+                          hipStream_t st)
+{
+    const dim3 grid((nel + 255) / 256);
+    if (elem == 8)
+        hipLaunchKernelGGL((lincomb_kernel<double>), grid, dim3(256), 0, st, nel, a, (const double *)x, b,
+                           (const double *)y, (double *)out);
+    else
+        hipLaunchKernelGGL((lincomb_kernel<float>), grid, dim3(256), 0, st, nel, a, (const float *)x, b,
+                           (const float *)y, (float *)out);
     return hipGetLastError();
 }
 

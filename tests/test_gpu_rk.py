@@ -1,0 +1,51 @@
+"""GPU parity of the s-stage Runge-Kutta time step with partial sums (sc_time_step, stages 2 and 3)
+against the oracle's (oracle.time_step_rk), FP64: 1e-11 of max |u| (D cancels by (alpha dx/theta)^2
+and enters up to the power s), and the mixed path at 1e-5; chunked y lines included."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_03041_amd import SC_F32_MIXED, Grid, ScError
+from paper_2007_03041_amd import workloads as W
+import paper_2007_03041_amd as sc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3])
+@pytest.mark.parametrize("n", [(64, 48), (40, 1100)])
+def test_rk_matches_oracle(gpu_lib, stages, n):
+    u0 = W.random_field((n[1], n[0]), index=60 + stages)
+    g = Grid(n, (0.0, 0.0), (2 * np.pi, 2 * np.pi * n[1] / n[0]))
+    dt = 0.02
+    c, nu_diff = (1.0, -0.7), 0.05
+    beta = 0.6
+    ref = oracle.time_step_rk(oracle.make_grid(g.n, g.lo, g.hi, g.bc), c, nu_diff, beta, dt, 6, 3, u0, stages)
+    u = torch.from_numpy(u0.copy()).cuda()
+    sc.time_step(u, g, 3, c=c, nu_diff=nu_diff, beta=beta, dt=dt, order=6, stages=stages)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_rk3_mixed_path(gpu_lib):
+    import dataclasses
+
+    n = (128, 96)
+    u0 = W.fourier_field(*n)
+    g = Grid(n, (0.0, 0.0), (2 * np.pi, 2 * np.pi * n[1] / n[0]))
+    ref = oracle.time_step_rk(oracle.make_grid(g.n, g.lo, g.hi, g.bc), (1.0, 1.0), 0.0, 0.35, 0.05, 4, 4, u0, 3)
+    u = torch.from_numpy(u0.astype(np.float32)).cuda()
+    sc.time_step(u, dataclasses.replace(g, dtype=SC_F32_MIXED), 4, c=(1.0, 1.0), beta=0.35, dt=0.05, order=4, stages=3)
+    torch.cuda.synchronize()
+    assert np.abs(u.double().cpu().numpy() - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+def test_rk_rejects_split_and_dirichlet(gpu_lib):
+    u = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(ScError):
+        sc.time_step(u, Grid((16, 16)), 1, c=(1.0, 1.0), dt=0.1, order=4, stages=2, split=True)
+    with pytest.raises(ScError):
+        sc.time_step(u, Grid((16, 16), bc=("dirichlet", "periodic")), 1, c=(1.0, 1.0), dt=0.1, order=4, stages=3)
+    with pytest.raises(ScError):
+        sc.time_step(u, Grid((16, 16)), 1, c=(1.0, 1.0), dt=0.1, order=4, stages=4)
