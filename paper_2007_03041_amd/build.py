@@ -12,8 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsc.so")
-SOURCES = ["sc_api.cpp", "sc_batch.cpp", "sc_coeffs.cpp", "sc_hj.cpp", "sc_hj_kernels.hip", "sc_kernels.hip", "sc_lp_f64_o4.hip", "sc_lp_f64_o6.hip",
-           "sc_lp_f32_o4.hip", "sc_lp_f32_o6.hip"]
+# the line-pass units first: they take longest
+SOURCES = ["sc_lp_f64_o4.hip", "sc_lp_f64_o6.hip", "sc_lp_f32_o4.hip", "sc_lp_f32_o6.hip", "sc_lp_f64_o4_full.hip",
+           "sc_lp_f64_o6_full.hip", "sc_lp_f32_o4_full.hip", "sc_lp_f32_o6_full.hip", "sc_api.cpp", "sc_batch.cpp",
+           "sc_coeffs.cpp", "sc_hj.cpp", "sc_hj_kernels.hip", "sc_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -98,6 +98,7 @@ int pick_variant(bool contig, int64_t n, int elem)
         if (n <= 256) return 0;   // 16 lines x 256
         if (n <= 512) return 10;  // 8 lines x 512
         if (n <= 1024) return 1;  // 4 lines x 1024
+        if (n <= 2048) return 16; // 2 lines x 2048
         if (n <= 4096) return 2;  // 1 line x 4096
         return 3;                 // 1 line x 8192; longer lines chunked
     }

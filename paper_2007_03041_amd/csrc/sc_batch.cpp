@@ -31,7 +31,7 @@ using namespace scx::host;
 namespace {
 
 // x-line variants a batch may use (see SC_VARIANTS)
-const int kBatchVariants[] = {14, 0, 10, 1, 9, 2, 3, 15};
+const int kBatchVariants[] = {14, 0, 10, 1, 16, 9, 2, 3, 15};
 
 struct Choice {
     int vid = -1;
@@ -65,7 +65,7 @@ Choice default_choice(const sc_batch_item &it, int elem)
 {
     Choice c;
     if (it.nlines >= 4) {
-        c.vid = it.n <= 256 ? 0 : it.n <= 512 ? 10 : it.n <= 1024 ? 1 : it.n <= 4096 ? 2 : 3;
+        c.vid = it.n <= 256 ? 0 : it.n <= 512 ? 10 : it.n <= 1024 ? 1 : it.n <= 2048 ? 16 : it.n <= 4096 ? 2 : 3;
     } else {
         c.vid = it.n <= 1024 ? 14 : it.n <= 4096 ? 2 : 3;
     }

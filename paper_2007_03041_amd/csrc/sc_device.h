@@ -129,6 +129,7 @@ constexpr int LDS_LIMIT = 160 * 1024;  // LDS per workgroup on gfx950
     X(12, 16, 32, false, 1024)     \
     X(13, 8, 32, false, 1024)      \
     X(14, 16, 1, true, 64)         \
-    X(15, 16, 1, true, 1024)
+    X(15, 16, 1, true, 1024)       \
+    X(16, 16, 2, true, 256)
 
 }  // namespace scx

@@ -5,10 +5,14 @@
 
 namespace scx {
 
-extern template hipError_t launch_line_pass_t<double, 4>(const PassArgs &, int, int, bool, hipStream_t);
-extern template hipError_t launch_line_pass_t<double, 6>(const PassArgs &, int, int, bool, hipStream_t);
-extern template hipError_t launch_line_pass_t<float, 4>(const PassArgs &, int, int, bool, hipStream_t);
-extern template hipError_t launch_line_pass_t<float, 6>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<double, 4, false>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<double, 4, true>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<double, 6, false>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<double, 6, true>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<float, 4, false>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<float, 4, true>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<float, 6, false>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_t<float, 6, true>(const PassArgs &, int, int, bool, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<double, 4>(const BatchLaunch &, int, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<double, 6>(const BatchLaunch &, int, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<float, 4>(const BatchLaunch &, int, hipStream_t);
@@ -213,12 +217,21 @@ bool variant_built(int vid, int elem)
 hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int mode, bool multi, hipStream_t st)
 {
     if (!variant_built(vid, elem)) return hipErrorInvalidValue;
+    // lines that are a whole number of chunks have no segment past their end: the kernels without
+    // the per-point end rules keep fewer registers live and reach a higher occupancy
+    const bool full = a.n % variant(vid).C() == 0;
     if (elem == 8) {
-        if (order == 4) return launch_line_pass_t<double, 4>(a, vid, mode, multi, st);
-        return launch_line_pass_t<double, 6>(a, vid, mode, multi, st);
+        if (order == 4)
+            return full ? launch_line_pass_t<double, 4, true>(a, vid, mode, multi, st)
+                        : launch_line_pass_t<double, 4, false>(a, vid, mode, multi, st);
+        return full ? launch_line_pass_t<double, 6, true>(a, vid, mode, multi, st)
+                    : launch_line_pass_t<double, 6, false>(a, vid, mode, multi, st);
     }
-    if (order == 4) return launch_line_pass_t<float, 4>(a, vid, mode, multi, st);
-    return launch_line_pass_t<float, 6>(a, vid, mode, multi, st);
+    if (order == 4)
+        return full ? launch_line_pass_t<float, 4, true>(a, vid, mode, multi, st)
+                    : launch_line_pass_t<float, 4, false>(a, vid, mode, multi, st);
+    return full ? launch_line_pass_t<float, 6, true>(a, vid, mode, multi, st)
+                : launch_line_pass_t<float, 6, false>(a, vid, mode, multi, st);
 }
 
 hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st)

@@ -43,8 +43,8 @@ int line_pass_batch_occupancy(int elem, int order, int vid, int mode);
 hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems, int64_t chunk_len,
                                     const double *g, double *ws, hipStream_t st);
 
-// one instantiation unit per (element type, order): sc_lp_<type>_o<order>.hip
-template <typename T, int ORDER>
+// one instantiation unit per (element type, order, full tiles or not): sc_lp_<type>_o<order>[_full].hip
+template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st);
 template <typename T, int ORDER>
 hipError_t launch_line_pass_batch_t(const BatchLaunch &b, int vid, hipStream_t st);

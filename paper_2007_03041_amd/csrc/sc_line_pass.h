@@ -167,6 +167,77 @@ __device__ __forceinline__ T line_value(const PA &a, const T *v, int64_t base, i
     return (T)s;
 }
 
+// Operand values each thread of a tile loads: TC lines x (C + order) points over NT threads.
+constexpr int tile_fill(int order, int S, int TC, int NT) { return (TC * ((NT / TC) * S + order) + NT - 1) / NT; }
+
+// Issues the global loads of one tile's operand values into registers: element e = tid + k NT of
+// the tile (line e / W, point cstart - order/2 + e % W along x; line e % TC, point e / TC along
+// y/z) goes to vals[k].  lb holds the TC line bases.  Periodic halos wrap; points outside a
+// Dirichlet line read 0 (they are filled from the end interpolant once the tile is in LDS).
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, class PA>
+__device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)], const PA &a, const T *v,
+                                          const int64_t *lb, int64_t line0, int64_t cstart, int tid)
+{
+    constexpr int H = ORDER / 2;
+    constexpr int C = (NT / TC) * S;
+    constexpr int W = C + 2 * H;
+    constexpr int FILL = tile_fill(ORDER, S, TC, NT);
+    const int ni = (int)a.n;
+    const bool wrap_many = (a.bc == 0) && (ni < C + 2 * H);
+    if (CONTIG && TC == 1) {
+        // element e = tid + k NT is point p = cstart - H + e of the one line of the tile
+        const int p0 = (int)cstart - H + tid;
+        const T *rowp = v + lb[0] + p0;
+        const bool lok = line0 < a.nlines;
+        // one load per element, from the in-line address plus the wrap of a periodic halo point: two
+        // alternative loads into one register would serialise the loads behind register reuse
+#pragma unroll
+        for (int k = 0; k < FILL; ++k) {
+            const int e = tid + k * NT;
+            const int p = p0 + k * NT;
+            bool ok = lok && e < W;
+            int dp = 0;
+            if (p < 0 || p >= ni) {
+                if (a.bc == 0) {
+                    int pw = p;
+                    if (wrap_many) {
+                        pw %= ni;
+                        if (pw < 0) pw += ni;
+                    } else {
+                        pw = p < 0 ? p + ni : p - ni;
+                    }
+                    dp = pw - p;
+                } else {
+                    ok = false;
+                }
+            }
+            vals[k] = ok ? ldg(rowp + k * NT + dp) : T(0);
+        }
+    } else {
+        const int64_t st = CONTIG ? 1 : a.stride;  // contiguous variants only run on stride-1 axes
+        const int c0 = (int)cstart - H;
+#pragma unroll
+        for (int k = 0; k < FILL; ++k) {
+            const int e = tid + k * NT;
+            const int cc = CONTIG ? e / W : e % TC;
+            const int q = CONTIG ? e % W : e / TC;
+            int p = c0 + q;
+            bool ok = (e < TC * W) && (line0 + cc < a.nlines);
+            if (a.bc == 0) {
+                if (wrap_many) {
+                    p %= ni;
+                    if (p < 0) p += ni;
+                } else {
+                    p = (p < 0) ? p + ni : (p >= ni ? p - ni : p);
+                }
+            } else {
+                ok = ok && (p >= 0 && p < ni);
+            }
+            vals[k] = ok ? ldg(v + lb[cc] + (int64_t)p * st) : T(0);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // The line pass.
 //   T       element type in memory and per-point arithmetic type (double or float)
@@ -180,6 +251,8 @@ __device__ __forceinline__ T line_value(const PA &a, const T *v, int64_t base, i
 //   NOPS    operators applied to the same operand (1 or 2)
 //   MULTI   partial sums with k > 1 (FUSED, periodic, one operator): the new operand of each
 //           power is shared through the tile
+//   FULL    every tile of the launch is full (the line length is a multiple of the chunk length):
+//           no segment reaches past a line end, and the per-point end rules are compiled out
 // ------------------------------------------------------------------------------------------
 template <bool B>
 struct BoolC {
@@ -196,7 +269,7 @@ struct Ptrs {
     const double *carry;
 };
 
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI>
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI, bool FULL>
 __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
 {
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
@@ -216,6 +289,7 @@ line_pass_batch(const BatchArgs *__restrict__ table,
 {
     constexpr int NOPS = 1;
     constexpr bool MULTI = false;
+    constexpr bool FULL = false;
     // the table and work list are read-only for the whole launch: reading them through the constant
     // address space makes every per-instance parameter a scalar load, as for kernel arguments
     typedef const BatchArgs __attribute__((address_space(4))) CBatchArgs;
@@ -244,7 +318,7 @@ line_pass_batch(const BatchArgs *__restrict__ table,
 // ------------------------------------------------------------------------------------------
 // Launch of one variant; variants whose LDS does not fit for T are not instantiated.
 // ------------------------------------------------------------------------------------------
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, int NOPS>
+template <typename T, int ORDER, bool FULL, int S, int TC, bool CONTIG, int NT, int NOPS>
 static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
     constexpr Variant V{S, TC, CONTIG, NT};
@@ -254,36 +328,37 @@ static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStrea
         const int64_t tiles = (a.nlines + TC - 1) / TC;
         if (mode == MODE_FUSED) {
             if (NOPS == 1 && multi)
-                hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, 1, true>), dim3(tiles), dim3(NT),
+                hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, 1, true, FULL>), dim3(tiles), dim3(NT),
                                    0, st, a);
             else
-                hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, NOPS, false>), dim3(tiles),
+                hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, NOPS, false, FULL>), dim3(tiles),
                                    dim3(NT), 0, st, a);
             return hipGetLastError();
         }
         const dim3 grid(tiles * a.nchunks);
         if (mode == MODE_AGG)
-            hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, NOPS, false>), grid, dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, NOPS, false, FULL>), grid, dim3(NT), 0, st, a);
         else
-            hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, NOPS, false>), grid, dim3(NT), 0, st,
+            hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, NOPS, false, FULL>), grid, dim3(NT), 0, st,
                                a);
         return hipGetLastError();
     }
 }
 
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT>
+template <typename T, int ORDER, bool FULL, int S, int TC, bool CONTIG, int NT>
 static hipError_t launch_variant(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
-    if (a.nops == 2) return launch_shape<T, ORDER, S, TC, CONTIG, NT, 2>(a, mode, false, st);
-    return launch_shape<T, ORDER, S, TC, CONTIG, NT, 1>(a, mode, multi, st);
+    if (FULL && a.n % ((NT / TC) * S) != 0) return hipErrorInvalidValue;
+    if (a.nops == 2) return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 2>(a, mode, false, st);
+    return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 1>(a, mode, multi, st);
 }
 
-template <typename T, int ORDER>
+template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st)
 {
     switch (vid) {
 #define SC_CASE(id, S, TC, CONTIG, NT) \
-    case id: return launch_variant<T, ORDER, S, TC, CONTIG, NT>(a, mode, multi, st);
+    case id: return launch_variant<T, ORDER, FULL, S, TC, CONTIG, NT>(a, mode, multi, st);
         SC_VARIANTS(SC_CASE)
 #undef SC_CASE
     }

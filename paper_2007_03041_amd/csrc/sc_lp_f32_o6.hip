@@ -3,7 +3,7 @@
 #include "sc_line_pass.h"
 
 namespace scx {
-template hipError_t launch_line_pass_t<float, 6>(const PassArgs &, int, int, bool, hipStream_t);
+template hipError_t launch_line_pass_t<float, 6, false>(const PassArgs &, int, int, bool, hipStream_t);
 template hipError_t launch_line_pass_batch_t<float, 6>(const BatchLaunch &, int, hipStream_t);
 template int line_pass_batch_occupancy_t<float, 6>(int, int);
 }  // namespace scx

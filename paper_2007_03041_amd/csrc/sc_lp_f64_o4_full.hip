@@ -1,0 +1,7 @@
+// Line-pass kernels for double elements, order-4 local quadrature, on lines that are a whole number
+// of chunks (no segment past a line end).
+#include "sc_line_pass.h"
+
+namespace scx {
+template hipError_t launch_line_pass_t<double, 4, true>(const PassArgs &, int, int, bool, hipStream_t);
+}  // namespace scx

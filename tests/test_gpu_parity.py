@@ -67,7 +67,7 @@ def test_config1_replicated_lines(gpu_lib):
 # ------------------------------------------------------------------------------ ragged 1-D lines
 CASES = []
 _r = np.random.default_rng(5)
-for n in (7, 9, 64, 100, 129, 511, 513, 1000, 2049, 4096, 4097, 9000):
+for n in (7, 9, 64, 100, 129, 511, 513, 1000, 2048, 2049, 4096, 4097, 9000, 16384):
     for bc in ("periodic", "dirichlet"):
         for order in (4, 6):
             CASES.append((n, bc, order, float(10 ** _r.uniform(-2, math.log10(20)))))
@@ -93,6 +93,33 @@ def test_ragged_lines_contiguous(gpu_lib, n, bc, order, nu):
         ref = oracle.apply_D_partial_sum(ogrid(g), 0, "0", order, alpha, 3, 1.0, v)
         got = host(sc.apply_D_partial_sum(dev(v), g, 0, "0", order, alpha, 3, 1.0))
         assert err(got, ref, np.abs(v).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ many long x lines
+LONG_CASES = [(2049, "periodic", 4), (2049, "dirichlet", 6), (4096, "periodic", 6), (4096, "dirichlet", 4)]
+
+
+@pytest.mark.parametrize("n,bc,order", LONG_CASES)
+def test_many_long_x_lines(gpu_lib, n, bc, order):
+    """One-line tiles (x lines of 1025..4096 points), more lines than the chip holds workgroups at
+    once, ragged and full lengths, one and two operators per pass."""
+    sc = gpu_lib
+    lines = 700
+    v = W.random_field((lines, n), index=60 + n)
+    g = Grid((n, lines), (0.0, 0.0), (2.0, 1.0), (bc, "periodic"))
+    alpha = 3.0 / g.dx(0)
+    gv = np.random.default_rng(n + 1).standard_normal((lines, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, op, order, alpha, 1, 1.0, v, gv)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, op, order, alpha, 1, 1.0,
+                                          g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(v).max()) < TOL, op
+    if bc == "periodic":
+        # two operators on the same operand in one x pass (advection and diffusion of a time step)
+        ref = oracle.time_step(ogrid(g), (0.7, -0.3), 0.05, 1.0, 0.5 / n, order, 1, v, split=True)
+        u = dev(v)
+        sc.time_step(u, g, 1, c=(0.7, -0.3), nu_diff=0.05, beta=1.0, dt=0.5 / n, order=order, split=True)
+        assert err(host(u), ref, np.abs(ref).max()) < TOL
 
 
 # ------------------------------------------------------------------------------ strided axes
