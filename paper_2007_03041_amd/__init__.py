@@ -29,7 +29,7 @@ _STATUS = {0: "SC_OK", -1: "SC_ERR_ARG", -2: "SC_ERR_SHAPE", -3: "SC_ERR_UNSUPPO
 # exported symbols of include/sc.h
 SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum",
            "sc_time_step", "sc_workspace_bytes", "sc_effective_dt", "sc_last_error",
-           "sc_timing_enable", "sc_timing_read", "sc_timing_reset",
+           "sc_timing_enable", "sc_timing_select", "sc_timing_read", "sc_timing_reset",
            "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_workspace_bytes",
            "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
            "sc_batch_describe", "sc_hj_workspace_bytes", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
@@ -124,6 +124,7 @@ def load():
     lib.sc_last_error.argtypes = []
     lib.sc_last_error.restype = c_char_p
     lib.sc_timing_enable.argtypes = [c_int]
+    lib.sc_timing_select.argtypes = [ctypes.c_char_p]
     lib.sc_timing_read.argtypes = [POINTER(c_char * 64), POINTER(c_double), POINTER(c_int), c_int]
     lib.sc_timing_read.restype = c_int
     lib.sc_timing_reset.argtypes = []
@@ -155,7 +156,7 @@ def load():
                                 c_void_p]
     lib.sc_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]
     for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum", "sc_time_step",
-              "sc_timing_enable", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
+              "sc_timing_enable", "sc_timing_select", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
               "sc_batch_apply_per_instance", "sc_batch_tune", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
               "sc_mlp_forward", "sc_mlp_grad", "sc_mlp_adam"):
         getattr(lib, f).restype = c_int
@@ -326,6 +327,12 @@ def effective_dt(grid: Grid, pde: sc_linear_pde) -> float:
 
 def timing_enable(on: bool = True):
     _check(load().sc_timing_enable(1 if on else 0))
+
+
+def timing_select(names=None):
+    """Time only the launches of these kernel names (None or empty: every launch)."""
+    sel = ",".join(names) if names else ""
+    _check(load().sc_timing_select(sel.encode() if sel else None))
 
 
 def timing_reset():

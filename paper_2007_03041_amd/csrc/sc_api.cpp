@@ -27,6 +27,7 @@ namespace host {
 
 std::mutex g_tmu;
 bool g_timing = false;
+std::vector<std::string> g_timing_only;
 std::vector<TimedLaunch> g_records;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
 size_t g_pool_used = 0;
@@ -108,8 +109,10 @@ int pick_variant(bool contig, int64_t n, int elem)
         return 12;  // 32 lines x 512; longer lines chunked
     }
     if (n <= 256) return 4;
-    if (n <= 512) return 5;
-    return 6;  // 16 lines x 1024; longer lines chunked
+    // 16 lines x 512 (two workgroups per CU); longer lines chunked, their carries formed inside the
+    // apply launch up to 16 chunks
+    if (n <= 8192) return 5;
+    return 6;  // 16 lines x 1024
 }
 
 // decay from the start of the last real wave-part of a tile to the tile's last real point
@@ -171,6 +174,7 @@ void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, in
     }
     P->dpart = std::exp(-nu * (double)S * (double)V.GW());
     P->dchunk = std::exp(-nu * (double)C);
+    P->dchunk_last = std::exp(-nu * (double)(ax.n - (nch - 1) * C));
     P->dlp_full = last_part_decay(nu, std::min<int64_t>(ax.n, C), V);
     P->dlp_last = last_part_decay(nu, ax.n - (nch - 1) * C, V);
     const double x = nu * (double)ax.ncells;  // alpha (b - a)
@@ -208,6 +212,9 @@ int64_t nchunks_for(const Axis &ax, int elem)
     const int64_t C = scx::variant(pick_variant(ax.stride == 1, ax.n, elem)).C();
     return (ax.n + C - 1) / C;
 }
+
+// chunked passes with at most this many chunks per line form their carries inside the apply launch
+constexpr int64_t kFuseCarryChunks = 16;
 
 // One pass along `dim`: out = acc_term + sum_ops scale * result(op).
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v,
@@ -256,11 +263,14 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     const int64_t ent = (int64_t)nops * ax.nlines * a.nchunks;
     a.agg = (double *)wsp;
     a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
+    // lines of few chunks: every apply tile forms its own carries from the chunk totals (one launch
+    // less); longer lines go through the carry launch
+    a.fuse_carry = a.nchunks <= kFuseCarryChunks ? 1 : 0;
     e = timed(contig ? "line_pass_agg_x" : "line_pass_agg_yz", st, [&](const char **) {
         return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_AGG, false, st);
     });
-    if (e == hipSuccess)
-        e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, C, st); });
+    if (e == hipSuccess && !a.fuse_carry)
+        e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, st); });
     if (e == hipSuccess)
         e = timed(contig ? "line_pass_apply_x" : "line_pass_apply_yz", st, [&](const char **) {
             return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_APPLY, false, st);
@@ -576,6 +586,24 @@ sc_status sc_timing_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on != 0;
+    return SC_OK;
+}
+
+sc_status sc_timing_select(const char *names)
+{
+    std::vector<std::string> sel;
+    if (names) {
+        const std::string all(names);
+        if (all.size() > 1023) return fail(SC_ERR_ARG, "timing selection longer than 1023 bytes");
+        size_t p = 0;
+        while (p <= all.size()) {
+            const size_t q = std::min(all.find(',', p), all.size());
+            if (q > p) sel.push_back(all.substr(p, q - p));
+            p = q + 1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing_only = std::move(sel);
     return SC_OK;
 }
 

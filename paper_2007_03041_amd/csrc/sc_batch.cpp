@@ -98,7 +98,7 @@ size_t item_chunk_doubles(const sc_batch_item &it, int64_t C)
 struct Launch {
     int kind = 0;  // 0: line pass, 1: chunk carry
     int vid = 0, mode = 0;
-    int64_t nwork = 0, grid = 0, chunk_len = 0;
+    int64_t nwork = 0, grid = 0;
     size_t off = 0;  // byte offset of the work list / item list in the device buffer
 };
 
@@ -193,7 +193,6 @@ sc_status build(sc_batch_plan p)
             const Variant &V = variant(vid);
             Launch L;
             L.vid = vid;
-            L.chunk_len = V.C();
             if (phase == 2) {
                 std::vector<int32_t> ids(kv.second.begin(), kv.second.end());
                 const size_t off = host.size();
@@ -242,7 +241,7 @@ hipError_t enqueue(sc_batch_plan p, const void *v, void *out, const double *g, v
         hipError_t e;
         auto run = [&](const char **) -> hipError_t {
             if (L.kind == 1)
-                return launch_chunk_carry_batch(table, (const int32_t *)(p->dev + L.off), (int)L.nwork, L.chunk_len, g,
+                return launch_chunk_carry_batch(table, (const int32_t *)(p->dev + L.off), (int)L.nwork, g,
                                                 (double *)ws, st);
             BatchLaunch b{table, (const BatchWork *)(p->dev + L.off), L.nwork, L.grid, v, out, g, (double *)ws, L.mode};
             return launch_line_pass_batch(b, p->elem, p->order, L.vid, st);

@@ -24,6 +24,7 @@ struct OpArgs {
     double dseg[12];        // d^{S 2^j}: decay across 2^j whole segments
     double dpart;           // d^{S GW}: decay across one wave-part of segments
     double dchunk;          // d^{C}: decay across one whole chunk
+    double dchunk_last;     // decay across the last chunk of a line (its real length)
     double dlp_full;        // decay from the start of the last real wave-part of a tile to the tile's
     double dlp_last;        //   last real point: full tile (or whole line) / last chunk of a line
     double inv1mmu;         // 1 / (1 - mu), mu = e^{-alpha (b - a)}
@@ -59,7 +60,7 @@ struct PassArgs {
     int32_t bc;             // 0 periodic, 1 Dirichlet
     int32_t acc_mode;       // 0 none, 1 add the operand v, 2 add acc
     int32_t nops;           // 1 or 2
-    int32_t pad_;
+    int32_t fuse_carry;     // chunked apply: each tile forms its chunk carries from the aggregates
     // Dirichlet ends: the one-sided stencils of the order/2 points nearest an end integrate the
     // interpolant through the `order` end values; extending the line by that interpolant's values
     // at m = 1..order/2 points beyond the end makes the centred interior stencil integrate the same

@@ -25,6 +25,7 @@ struct TimedLaunch {
 };
 extern std::mutex g_tmu;
 extern bool g_timing;
+extern std::vector<std::string> g_timing_only;  // empty: every launch is timed
 extern std::vector<TimedLaunch> g_records;
 extern std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
 extern size_t g_pool_used;
@@ -32,7 +33,12 @@ extern size_t g_pool_used;
 template <typename F>
 hipError_t timed(const char *fallback_name, hipStream_t st, F &&launch)
 {
-    if (!g_timing) {
+    bool on = g_timing;
+    if (on && !g_timing_only.empty()) {
+        on = false;
+        for (const auto &s : g_timing_only) on = on || s == fallback_name;
+    }
+    if (!on) {
         const char *nm = fallback_name;
         return launch(&nm);
     }

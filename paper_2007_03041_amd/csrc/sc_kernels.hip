@@ -25,8 +25,7 @@ extern template int line_pass_batch_occupancy_t<float, 6>(int, int);
 // Chunk carries of chunked passes: one thread per (op, line) walks the chunk totals in both
 // directions (Sec. 3, eqs. (Left-/Right-moving integral DD) with exact attenuation factors) and
 // forms the boundary constants.
-__device__ void chunk_carry_one(const PassArgs &a, const double *agg, double *carry, const double *g,
-                                int64_t chunk_len, int64_t idx)
+__device__ void chunk_carry_one(const PassArgs &a, const double *agg, double *carry, const double *g, int64_t idx)
 {
     const int o = (int)(idx / a.nlines);
     const int64_t L = idx % a.nlines;
@@ -34,59 +33,41 @@ __device__ void chunk_carry_one(const PassArgs &a, const double *agg, double *ca
     const int64_t nch = a.nchunks;
     const double *ag = agg + ((int64_t)o * a.nlines + L) * nch * 3;
     double *cr = carry + ((int64_t)o * a.nlines + L) * nch * 2;
-    const int64_t len_last = a.n - (nch - 1) * chunk_len;
-    const double d_last = exp(-P.nu * (double)len_last);
     double E = 0.0;
     for (int64_t ch = 0; ch < nch; ++ch) {
         cr[2 * ch + 0] = E;
-        E = fma(ch == nch - 1 ? d_last : P.dchunk, E, ag[3 * ch + 0]);
+        E = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, E, ag[3 * ch + 0]);
     }
     double F = 0.0;
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
         cr[2 * ch + 1] = F;
-        F = fma(ch == nch - 1 ? d_last : P.dchunk, F, ag[3 * ch + 1]);
+        F = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, F, ag[3 * ch + 1]);
     }
-    const double IRn = E, IL0 = F, J0 = ag[2];
+    const double ga = (a.bc == 1 && g) ? g[2 * L + 0] : 0.0;
+    const double gb = (a.bc == 1 && g) ? g[2 * L + 1] : 0.0;
     double Ap = 0.0, Bp = 0.0;
-    if (a.bc == 0) {
-        Ap = fma(P.d, IRn, J0) * P.inv1mmu;
-        Bp = IL0 * P.inv1mmu;
-    } else {
-        const double ga = g ? g[2 * L + 0] : 0.0;
-        const double gb = g ? g[2 * L + 1] : 0.0;
-        if (P.op == 1) {
-            Ap = ga;
-        } else if (P.op == 0) {
-            Bp = gb;
-        } else {
-            const double r0 = ga - 0.5 * IL0, r1 = gb - 0.5 * IRn;
-            const double det = 1.0 - P.mu * P.mu;
-            Ap = 2.0 * (r0 - P.mu * r1) / det;
-            Bp = 2.0 * (r1 - P.mu * r0) / det;
-        }
-    }
+    boundary_constants(P, a.bc, E, F, ag[2], ga, gb, Ap, Bp);
     double *ab = carry + 2 * (int64_t)a.nops * a.nlines * nch + 2 * idx;
     ab[0] = Ap;
     ab[1] = Bp;
 }
 
-__global__ void __launch_bounds__(256) chunk_carry(const PassArgs a, int64_t chunk_len)
+__global__ void __launch_bounds__(256) chunk_carry(const PassArgs a)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)a.nops * a.nlines) return;
-    chunk_carry_one(a, a.agg, const_cast<double *>(a.carry), a.g, chunk_len, idx);
+    chunk_carry_one(a, a.agg, const_cast<double *>(a.carry), a.g, idx);
 }
 
 // Batched chunk carries: workgroup b serves every (operator, line) of instance items[b].
 __global__ void __launch_bounds__(256) chunk_carry_batch(const BatchArgs *__restrict__ table,
-                                                         const int32_t *__restrict__ items, int64_t chunk_len,
-                                                         const double *gbase, double *wsbase)
+                                                         const int32_t *__restrict__ items, const double *gbase,
+                                                         double *wsbase)
 {
     const BatchArgs &b = table[items[blockIdx.x]];
     const int64_t cnt = (int64_t)b.a.nops * b.a.nlines;
     for (int64_t idx = threadIdx.x; idx < cnt; idx += blockDim.x)
-        chunk_carry_one(b.a, wsbase + b.agg_off, wsbase + b.carry_off, b.g_off >= 0 ? gbase + b.g_off : nullptr,
-                        chunk_len, idx);
+        chunk_carry_one(b.a, wsbase + b.agg_off, wsbase + b.carry_off, b.g_off >= 0 ? gbase + b.g_off : nullptr, idx);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -254,18 +235,18 @@ int line_pass_batch_occupancy(int elem, int order, int vid, int mode)
     return order == 4 ? line_pass_batch_occupancy_t<float, 4>(vid, mode) : line_pass_batch_occupancy_t<float, 6>(vid, mode);
 }
 
-hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems, int64_t chunk_len,
+hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems,
                                     const double *g, double *ws, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(chunk_carry_batch, dim3(nitems), dim3(256), 0, st, table, items, chunk_len, g, ws);
+    hipLaunchKernelGGL(chunk_carry_batch, dim3(nitems), dim3(256), 0, st, table, items, g, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st)
+hipError_t launch_chunk_carry(const PassArgs &a, hipStream_t st)
 {
     const int64_t nthr = (int64_t)a.nops * a.nlines;
-    hipLaunchKernelGGL(chunk_carry, dim3((nthr + 255) / 256), dim3(256), 0, st, a, chunk_len);
+    hipLaunchKernelGGL(chunk_carry, dim3((nthr + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ bool variant_built(int vid, int elem);
 
 // elem = 8 (FP64) or 4 (FP32 data, mixed-precision carries)
 hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int mode, bool multi, hipStream_t st);
-hipError_t launch_chunk_carry(const PassArgs &a, int64_t chunk_len, hipStream_t st);
+hipError_t launch_chunk_carry(const PassArgs &a, hipStream_t st);
 hipError_t launch_local_quad(const PassArgs &a, int elem, int order, void *JL, void *JR, hipStream_t st);
 hipError_t launch_sweep(const PassArgs &a, int elem, const void *JL, const void *JR, void *IL, void *IR,
                         double *ends, hipStream_t st);
@@ -40,7 +40,7 @@ struct BatchLaunch {
 hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st);
 // resident workgroups per CU of the batched pass (0 if the variant is not built for x lines)
 int line_pass_batch_occupancy(int elem, int order, int vid, int mode);
-hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems, int64_t chunk_len,
+hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems,
                                     const double *g, double *ws, hipStream_t st);
 
 // one instantiation unit per (element type, order, full tiles or not): sc_lp_<type>_o<order>[_full].hip

@@ -134,6 +134,75 @@ __device__ __forceinline__ double decayed(double A, double nu, int64_t m)
     return x > 745.0 ? 0.0 : A * exp(-x);
 }
 
+// Boundary constants A', B' of one line from its sweep totals: I_R at the last point (IRn), I_L at
+// the first point (IL0) and J_R at x_0 (J0).  Periodic lines (Sec. 2.3): A' = (d IRn + J0)/(1 - mu),
+// B' = IL0/(1 - mu).  Dirichlet lines: the end values ga, gb fix them; for L_0 through the 2x2
+// system 0.5 I_L(a) + A + B mu = ga, 0.5 I_R(b) + A mu + B = gb (A' = 2A, B' = 2B).
+template <class OA>
+__device__ __forceinline__ void boundary_constants(const OA &P, int bc, double IRn, double IL0, double J0, double ga,
+                                                   double gb, double &Ap, double &Bp)
+{
+    Ap = 0.0;
+    Bp = 0.0;
+    if (bc == 0) {
+        Ap = fma(P.d, IRn, J0) * P.inv1mmu;
+        Bp = IL0 * P.inv1mmu;
+    } else if (P.op == 1) {
+        Ap = ga;
+    } else if (P.op == 0) {
+        Bp = gb;
+    } else {
+        const double r0 = ga - 0.5 * IL0, r1 = gb - 0.5 * IRn;
+        const double det = 1.0 - P.mu * P.mu;
+        Ap = 2.0 * (r0 - P.mu * r1) / det;
+        Bp = 2.0 * (r1 - P.mu * r0) / det;
+    }
+}
+
+// Chunk carries of line L, operator P, from the per-chunk totals ag[3 ch + {0, 1, 2}] (forward,
+// backward, J_R at the chunk's first point) of its nch chunks: the forward carry into chunk `want`
+// (cf), the backward carry into it (cb), and the line totals IRn = I_R at the last point and
+// IL0 = I_L at the first (Sec. 3: a block's integral is its own sweep plus the attenuated sweeps
+// of the blocks before it).
+// The totals are read four chunks at a time, so their loads overlap instead of each waiting behind
+// the previous step of the recurrence.
+template <class OA>
+__device__ __forceinline__ void chunk_scan(const OA &P, const double *ag, int64_t nch, int64_t want, double &cf,
+                                           double &cb, double &IRn, double &IL0)
+{
+    constexpr int B = 4;
+    double E = 0.0;
+    for (int64_t c0 = 0; c0 < nch; c0 += B) {
+        double t[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) t[j] = (c0 + j < nch) ? ag[3 * (c0 + j) + 0] : 0.0;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int64_t ch = c0 + j;
+            if (ch < nch) {
+                if (ch == want) cf = E;
+                E = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, E, t[j]);
+            }
+        }
+    }
+    double F = 0.0;
+    for (int64_t c1 = nch - 1; c1 >= 0; c1 -= B) {
+        double t[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) t[j] = (c1 - j >= 0) ? ag[3 * (c1 - j) + 1] : 0.0;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int64_t ch = c1 - j;
+            if (ch >= 0) {
+                if (ch == want) cb = F;
+                F = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, F, t[j]);
+            }
+        }
+    }
+    IRn = E;
+    IL0 = F;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldg(const T *p)
 {

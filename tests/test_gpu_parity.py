@@ -122,6 +122,22 @@ def test_many_long_x_lines(gpu_lib, n, bc, order):
         assert err(host(u), ref, np.abs(ref).max()) < TOL
 
 
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_lines_of_many_chunks(gpu_lib, bc):
+    """x lines of 18 chunks (ragged): the chunk carries come from their own launch, where lines of
+    at most 16 chunks form them inside the apply launch."""
+    sc = gpu_lib
+    n, lines = 140000, 3
+    v = W.random_field((lines, n), index=77)
+    g = Grid((n, lines), (0.0, 0.0), (1.0, 1.0), (bc, "periodic"))
+    alpha = 0.02 / g.dx(0)
+    gv = np.random.default_rng(78).standard_normal((lines, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), 0, op, 4, alpha, 1, 1.0, v, gv)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 0, op, 4, alpha, 1, 1.0, g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(v).max()) < TOL, op
+
+
 # ------------------------------------------------------------------------------ strided axes
 SHAPES = [
     ((41, 37, 5), ("periodic", "dirichlet", "periodic")),
