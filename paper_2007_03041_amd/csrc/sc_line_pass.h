@@ -203,6 +203,32 @@ __device__ __forceinline__ void chunk_scan(const OA &P, const double *ag, int64_
     IL0 = F;
 }
 
+// chunk_scan over totals already in registers: forward totals tf[ch], backward totals tb[ch] of
+// nch <= M chunks (same operations in the same order)
+template <int M, class OA>
+__device__ __forceinline__ void chunk_scan_regs(const OA &P, const double (&tf)[M], const double (&tb)[M], int64_t nch,
+                                                int64_t want, double &cf, double &cb, double &IRn, double &IL0)
+{
+    double E = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < M; ++ch) {
+        if (ch < nch) {
+            if (ch == want) cf = E;
+            E = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, E, tf[ch]);
+        }
+    }
+    double F = 0.0;
+#pragma unroll
+    for (int ch = M - 1; ch >= 0; --ch) {
+        if (ch < nch) {
+            if (ch == want) cb = F;
+            F = fma(ch == nch - 1 ? P.dchunk_last : P.dchunk, F, tb[ch]);
+        }
+    }
+    IRn = E;
+    IL0 = F;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldg(const T *p)
 {
