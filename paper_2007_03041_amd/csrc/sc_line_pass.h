@@ -130,6 +130,7 @@ __device__ __forceinline__ double dseg_pow(const OA &P, int m)
 __device__ __forceinline__ double decayed(double A, double nu, int64_t m)
 {
     if (A == 0.0 || m < 0) return 0.0;
+    if (m == 0) return A;
     const double x = nu * (double)m;
     return x > 745.0 ? 0.0 : A * exp(-x);
 }
