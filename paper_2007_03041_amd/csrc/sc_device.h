@@ -99,12 +99,12 @@ struct Variant {
     constexpr int C() const { return G() * S; }
     constexpr int GW() const { return contig ? (G() < WAVE ? G() : WAVE) : WAVE / TC; }
     constexpr int NP() const { return G() / GW(); }
-    // static LDS of the line pass with this shape: the tile (padded, odd line stride), line bases,
+    // static LDS of the line pass with this shape: the tile (line stride as in the kernel), line bases,
     // four carry tables, J_R(x_0), boundary terms and two decay tables
     constexpr int lds_bytes(int elem, int order, int nops) const
     {
         const int W = C() + order;
-        const int LS = (W + W / S + 1) | 1;
+        const int LS = (!contig && elem == 8) ? (((W + 31) & ~31) + 1) : ((W + W / S + 1) | 1);
         return TC * LS * elem + TC * 8 + 4 * nops * TC * NP() * 8 + nops * TC * 8 + nops * TC * 3 * 8 +
                nops * (GW() + 1) * 8 + nops * (NP() + 1) * 8;
     }

@@ -309,6 +309,17 @@ __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)]
             }
             vals[k] = ok ? ldg(rowp + k * NT + dp) : T(0);
         }
+    } else if (!CONTIG && (int)cstart - H >= 0 && (int)cstart - H + W <= ni) {
+        // strided tile inside its lines: thread tid loads line tid % TC, rows tid / TC + k NT / TC
+        const int cc = tid % TC;
+        const bool ok = line0 + cc < a.nlines;
+        const T *q = v + lb[cc] + (int64_t)((int)cstart - H + tid / TC) * a.stride;
+        const int64_t step = (int64_t)(NT / TC) * a.stride;
+#pragma unroll
+        for (int k = 0; k < FILL; ++k) {
+            vals[k] = (ok && tid + k * NT < TC * W) ? ldg(q) : T(0);
+            q += step;
+        }
     } else {
         const int64_t st = CONTIG ? 1 : a.stride;  // contiguous variants only run on stride-1 axes
         const int c0 = (int)cstart - H;
