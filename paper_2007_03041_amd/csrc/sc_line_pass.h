@@ -270,7 +270,9 @@ constexpr int tile_fill(int order, int S, int TC, int NT) { return (TC * ((NT / 
 // the tile (line e / W, point cstart - order/2 + e % W along x; line e % TC, point e / TC along
 // y/z) goes to vals[k].  lb holds the TC line bases.  Periodic halos wrap; points outside a
 // Dirichlet line read 0 (they are filled from the end interpolant once the tile is in LDS).
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, class PA>
+// FULL: the line length is a whole number of chunks, so on one-line tiles only the first and the
+// last group of NT elements can fall outside the line.
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL, class PA>
 __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)], const PA &a, const T *v,
                                           const int64_t *lb, int64_t line0, int64_t cstart, int tid)
 {
@@ -284,14 +286,25 @@ __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)]
         // element e = tid + k NT is point p = cstart - H + e of the one line of the tile
         const int p0 = (int)cstart - H + tid;
         const T *rowp = v + lb[0] + p0;
-        const bool lok = line0 < a.nlines;
+        // (the tile's line exists or not for the whole workgroup: one uniform branch, so no element's
+        // load sits in a branch of its own)
+        if (line0 >= a.nlines) {
+#pragma unroll
+            for (int k = 0; k < FILL; ++k) vals[k] = T(0);
+            return;
+        }
         // one load per element, from the in-line address plus the wrap of a periodic halo point: two
         // alternative loads into one register would serialise the loads behind register reuse
 #pragma unroll
         for (int k = 0; k < FILL; ++k) {
             const int e = tid + k * NT;
             const int p = p0 + k * NT;
-            bool ok = lok && e < W;
+            if (FULL && NT >= ORDER && k > 0 && k < FILL - 1) {
+                // elements NT .. C - 1 of the tile: points cstart - H + NT .. cstart + C - H - 1
+                vals[k] = ldg(rowp + k * NT);
+                continue;
+            }
+            bool ok = e < W;
             int dp = 0;
             if (p < 0 || p >= ni) {
                 if (a.bc == 0) {
