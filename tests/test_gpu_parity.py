@@ -380,3 +380,34 @@ def test_repeat_runs_bitwise_identical(gpu_lib):
     a = host(sc.apply_invL(v, g, 1, "R", 4, 30.0)).copy()
     b = host(sc.apply_invL(v, g, 1, "R", 4, 30.0))
     assert np.array_equal(a, b)
+
+
+def test_timing_select_times_only_the_named_kernels(gpu_lib):
+    """sc_timing_select: with a selection only the named launches carry events; without one every
+    launch of the library does."""
+    sc = gpu_lib
+    n = (2048, 64)
+    g = Grid(n)
+    u = dev(W.random_field((64, 2048), index=5))
+    try:
+        sc.timing_reset()
+        sc.timing_select(["line_pass_fused_yz"])
+        sc.timing_enable(True)
+        sc.time_step(u, g, 2, c=(1.0, 1.0), nu_diff=0.5, beta=1.0, dt=1.0 / 2048, order=4, split=True)
+        torch.cuda.synchronize()
+        sc.timing_enable(False)
+        sel = sc.timing_read()
+        sc.timing_reset()
+        sc.timing_select(None)
+        sc.timing_enable(True)
+        sc.time_step(u, g, 2, c=(1.0, 1.0), nu_diff=0.5, beta=1.0, dt=1.0 / 2048, order=4, split=True)
+        torch.cuda.synchronize()
+        sc.timing_enable(False)
+        every = sc.timing_read()
+    finally:
+        sc.timing_enable(False)
+        sc.timing_reset()
+        sc.timing_select(None)
+    assert set(sel) == {"line_pass_fused_yz"} and sel["line_pass_fused_yz"][1] == 2
+    assert {"line_pass_fused_x", "line_pass_fused_yz"} <= set(every)
+    assert all(cnt == 2 and ms > 0 for ms, cnt in every.values())
