@@ -60,6 +60,83 @@ __device__ __forceinline__ R shfl_down_r(R x, int delta)
     return __shfl_down(x, (unsigned)delta, WAVE);
 }
 
+// A double moved between lanes by one DPP pattern (both halves alike).  Lanes whose source lies
+// outside the pattern's range, or whose row is not in ROW_MASK, receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+enum : int {
+    DPP_ROW_SHL0 = 0x100,  // + k: row_shl:k (lane i of a row of 16 reads lane i + k of its row)
+    DPP_ROW_SHR0 = 0x110,  // + k: row_shr:k (lane i reads lane i - k of its row)
+    DPP_WAVE_SHL1 = 0x130, // lane i reads lane i + 1
+    DPP_WAVE_SHR1 = 0x138, // lane i reads lane i - 1
+    DPP_ROW_BCAST15 = 0x142, // the rows in the mask read lane 15 of the row below them
+    DPP_ROW_BCAST31 = 0x143, // the rows in the mask read lane 31
+};
+
+// Inclusive scans x_i <- sum_j D^{|i-j|} a_j over the GW consecutive lanes of each wave part
+// (GW = 16, 32 or 64; gl = lane mod GW), for the segment totals of contiguous tiles:
+// Kogge-Stone with DPP row shifts inside each row of 16 lanes (decays D^k from dseg), then the
+// carries across rows with per-lane decays pw[m] = D^m.  Forward: rows 1 and 3 take lane 15 of the
+// row below by row broadcast, then rows 2 and 3 take lane 31.  Backward: row r takes the first
+// lane of row r + 1, read as a scalar, from the top row down.
+template <int GW, class OA>
+__device__ __forceinline__ double scan_fwd_dpp(double x, const OA &P, const double *pw, int gl)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if ((1 << s) < GW) {
+            double y;
+            if (s == 0) y = dpp_d<DPP_ROW_SHR0 + 1, 0xF>(x);
+            else if (s == 1) y = dpp_d<DPP_ROW_SHR0 + 2, 0xF>(x);
+            else if (s == 2) y = dpp_d<DPP_ROW_SHR0 + 4, 0xF>(x);
+            else y = dpp_d<DPP_ROW_SHR0 + 8, 0xF>(x);
+            x = fma(P.dseg[s], y, x);
+        }
+    }
+    if constexpr (GW > 16) x = fma(pw[(gl & 15) + 1], dpp_d<DPP_ROW_BCAST15, 0xA>(x), x);
+    if constexpr (GW > 32) x = fma(pw[gl >= 32 ? gl - 31 : 0], dpp_d<DPP_ROW_BCAST31, 0xC>(x), x);
+    return x;
+}
+template <int GW, class OA>
+__device__ __forceinline__ double scan_bwd_dpp(double x, const OA &P, const double *pw, int gl)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if ((1 << s) < GW) {
+            double y;
+            if (s == 0) y = dpp_d<DPP_ROW_SHL0 + 1, 0xF>(x);
+            else if (s == 1) y = dpp_d<DPP_ROW_SHL0 + 2, 0xF>(x);
+            else if (s == 2) y = dpp_d<DPP_ROW_SHL0 + 4, 0xF>(x);
+            else y = dpp_d<DPP_ROW_SHL0 + 8, 0xF>(x);
+            x = fma(P.dseg[s], y, x);
+        }
+    }
+    const int lane = (int)(__lane_id());
+    if constexpr (GW == 32) {
+        // two wave parts per wave: rows 0 and 2 take the first lane of rows 1 and 3
+        const double c1 = readlane_d(x, 16), c3 = readlane_d(x, 48);
+        if ((lane & 16) == 0) x = fma(pw[16 - (gl & 15)], lane < 32 ? c1 : c3, x);
+    } else if constexpr (GW == 64) {
+        const double c3 = readlane_d(x, 48);
+        if ((lane >> 4) == 2) x = fma(pw[48 - gl], c3, x);
+        const double c2 = readlane_d(x, 32);
+        if ((lane >> 4) == 1) x = fma(pw[32 - gl], c2, x);
+        const double c1 = readlane_d(x, 16);
+        if ((lane >> 4) == 0) x = fma(pw[16 - gl], c1, x);
+    }
+    return x;
+}
+
 __device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
