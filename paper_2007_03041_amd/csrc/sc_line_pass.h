@@ -192,6 +192,73 @@ __device__ __forceinline__ void comp_axpy(float Dh, float Dl, float yh, float yl
     xh = h;
 }
 
+// The scans above on (hi, lo) float pairs with the compensated step comp_axpy, for FP32 tiles.  A
+// lane whose source lies outside the pattern keeps its pair, as in the shuffle form; per-lane decays
+// pw[m] (FP64) enter as hi + lo.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+__device__ __forceinline__ void comp_axpy_d(double D, float yh, float yl, float &xh, float &xl)
+{
+    const float Dh = (float)D;
+    comp_axpy(Dh, (float)(D - (double)Dh), yh, yl, xh, xl);
+}
+template <int GW, class OA>
+__device__ __forceinline__ void scan_fwd_dpp_f(float &xh, float &xl, const OA &P, const double *pw, int gl)
+{
+    const int r16 = gl & 15;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if ((1 << s) < GW) {
+            float yh, yl;
+            if (s == 0) yh = dpp_f<DPP_ROW_SHR0 + 1, 0xF>(xh), yl = dpp_f<DPP_ROW_SHR0 + 1, 0xF>(xl);
+            else if (s == 1) yh = dpp_f<DPP_ROW_SHR0 + 2, 0xF>(xh), yl = dpp_f<DPP_ROW_SHR0 + 2, 0xF>(xl);
+            else if (s == 2) yh = dpp_f<DPP_ROW_SHR0 + 4, 0xF>(xh), yl = dpp_f<DPP_ROW_SHR0 + 4, 0xF>(xl);
+            else yh = dpp_f<DPP_ROW_SHR0 + 8, 0xF>(xh), yl = dpp_f<DPP_ROW_SHR0 + 8, 0xF>(xl);
+            if (r16 >= (1 << s)) comp_axpy(P.dseg_hi[s], P.dseg_lo[s], yh, yl, xh, xl);
+        }
+    }
+    if constexpr (GW > 16) {
+        const float yh = dpp_f<DPP_ROW_BCAST15, 0xA>(xh), yl = dpp_f<DPP_ROW_BCAST15, 0xA>(xl);
+        if (gl & 16) comp_axpy_d(pw[r16 + 1], yh, yl, xh, xl);
+    }
+    if constexpr (GW > 32) {
+        const float yh = dpp_f<DPP_ROW_BCAST31, 0xC>(xh), yl = dpp_f<DPP_ROW_BCAST31, 0xC>(xl);
+        if (gl >= 32) comp_axpy_d(pw[gl - 31], yh, yl, xh, xl);
+    }
+}
+template <int GW, class OA>
+__device__ __forceinline__ void scan_bwd_dpp_f(float &xh, float &xl, const OA &P, const double *pw, int gl)
+{
+    const int r16 = gl & 15;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if ((1 << s) < GW) {
+            float yh, yl;
+            if (s == 0) yh = dpp_f<DPP_ROW_SHL0 + 1, 0xF>(xh), yl = dpp_f<DPP_ROW_SHL0 + 1, 0xF>(xl);
+            else if (s == 1) yh = dpp_f<DPP_ROW_SHL0 + 2, 0xF>(xh), yl = dpp_f<DPP_ROW_SHL0 + 2, 0xF>(xl);
+            else if (s == 2) yh = dpp_f<DPP_ROW_SHL0 + 4, 0xF>(xh), yl = dpp_f<DPP_ROW_SHL0 + 4, 0xF>(xl);
+            else yh = dpp_f<DPP_ROW_SHL0 + 8, 0xF>(xh), yl = dpp_f<DPP_ROW_SHL0 + 8, 0xF>(xl);
+            if (r16 + (1 << s) < 16 && r16 + (1 << s) < GW) comp_axpy(P.dseg_hi[s], P.dseg_lo[s], yh, yl, xh, xl);
+        }
+    }
+    const int lane = (int)(__lane_id());
+    auto rd = [](float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); };
+    if constexpr (GW == 32) {
+        const float h1 = rd(xh, 16), l1 = rd(xl, 16), h3 = rd(xh, 48), l3 = rd(xl, 48);
+        if ((lane & 16) == 0) comp_axpy_d(pw[16 - r16], lane < 32 ? h1 : h3, lane < 32 ? l1 : l3, xh, xl);
+    } else if constexpr (GW == 64) {
+        const float h3 = rd(xh, 48), l3 = rd(xl, 48);
+        if ((lane >> 4) == 2) comp_axpy_d(pw[48 - gl], h3, l3, xh, xl);
+        const float h2 = rd(xh, 32), l2 = rd(xl, 32);
+        if ((lane >> 4) == 1) comp_axpy_d(pw[32 - gl], h2, l2, xh, xl);
+        const float h1 = rd(xh, 16), l1 = rd(xl, 16);
+        if ((lane >> 4) == 0) comp_axpy_d(pw[16 - gl], h1, l1, xh, xl);
+    }
+}
+
 // d^{S m} for 0 <= m < 2^12 from the binary powers d^{S 2^j}
 template <class OA>
 __device__ __forceinline__ double dseg_pow(const OA &P, int m)
