@@ -374,10 +374,13 @@ __device__ __forceinline__ void chunk_scan_regs(const OA &P, const double (&tf)[
     IL0 = F;
 }
 
+// Operand loads are ordinary cached loads: a window's halo rows are read again by the neighbouring
+// segment's thread, and a streaming (non-temporal) hint evicted them before that second read (the
+// aggregate launch then fetched 14 % more than the field and ran 25 % longer).
 template <typename T>
 __device__ __forceinline__ T ldg(const T *p)
 {
-    return __builtin_nontemporal_load(p);
+    return *p;
 }
 
 // Value at point p of the line at `base`: periodic wrap, or for Dirichlet lines the extension of
