@@ -1,5 +1,5 @@
 // sc_line_pass.h -- the line-pass kernel of the successive-convolution fast summation (gfx950),
-// included by one instantiation unit per (element type, order).
+// included by one instantiation unit per (element type, order, full tiles or not).
 //
 // One pass applies up to two operators L_op^{-1} (or D = I - L_op^{-1} and its partial sums) along
 // one axis of a dense array, line by line (Sec. 2.2: the directions stay uncoupled).
@@ -8,10 +8,12 @@
 //   thread    = one segment of S consecutive points of one line (G segments per line)
 //
 // Per workgroup, with one HBM read of the operand and one write of the result:
-//   1. coalesced load of the tile into LDS in [line][point] layout (one pad element per segment
-//      against bank conflicts).  Along x the lanes run along the line; along y/z they run across TC
-//      adjacent lines, so y/z tiles are transposed through LDS.  Each thread then holds the window
-//      of S + order operand values around its segment in registers.
+//   1. coalesced load of the tile into LDS in [line][point] layout.  Along x the lanes run along the
+//      line and the tile transposes the data into per-thread segments (one pad element per segment
+//      against bank conflicts); along y/z the lanes run across TC adjacent lines, the FP64 tile is
+//      unpadded with a line stride of 1 mod 32, and the read-only aggregate launch skips the tile
+//      and reads each window straight from memory.  Each thread then holds the window of S + order
+//      operand values around its segment in registers.
 //   2. segment totals of the two sweeps (Sec. 2.4 recurrences).  In the interior they are linear
 //      in the window, so each is one dot product with coefficients precomputed on the host (kR,
 //      kL); segments at line ends and in the padding use the point-by-point local integrals of
@@ -19,10 +21,11 @@
 //      extending the line beyond each end with the interpolant of its end values, so the centred
 //      stencil integrates the same polynomial there.
 //   3. the segments are combined by a first-order linear-recurrence scan over (decay, value) pairs:
-//      Kogge-Stone with wavefront shuffles inside a wave (decay d^{S 2^j}) and one LDS exchange
-//      between the waves of a line (Sec. 3, eqs. (Left-/Right-moving integral DD): a block's
-//      integral = its own sweep + attenuated contributions of the others).  Lines longer than one
-//      tile are chunked: an aggregate launch, a carry launch and an apply launch.
+//      Kogge-Stone inside a wave (decay d^{S 2^j}; DPP lane moves on x tiles, shuffles on y/z
+//      tiles) and one LDS exchange between the waves of a line (Sec. 3, eqs. (Left-/Right-moving
+//      integral DD): a block's integral = its own sweep + attenuated contributions of the others).
+//      Lines longer than one tile are chunked: an aggregate launch, then an apply launch that forms
+//      its carries from the chunk totals (lines of more than 16 chunks: a carry launch between).
 //   4. the line totals give the boundary constants in FP64 (Sec. 2.3 periodic constants; Dirichlet
 //      end values through the 2x2 system whose inverse has the form of Sec. 3.3).
 //   5. each thread re-sweeps its segment from the exact carries: the forward sweep adds its share
