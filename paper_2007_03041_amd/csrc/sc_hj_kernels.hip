@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
     __shared__ float feat[512][MLP_IN];
     __shared__ float hid[4][16][33];
     __shared__ float zo[512][4];
-    __shared__ double red[2][256];
+    __shared__ double red[2][4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int64_t p = (int64_t)blockIdx.x * 256 + tid;
@@ -241,11 +241,19 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
         wenoz(sL, A.d, oL);
     }
     if (MODE == HJ_LEARNED) {
+        // Every tile below reads and writes only its own wave's rows of feat, hid and zo (tile T of
+        // wave wv covers its points wv*64 + 16 (T mod 4) ..., stencil R for T < 4, L after), so the
+        // waves synchronise with themselves only: LDS accesses of one wave complete in order, and
+        // the fences keep the compiler from moving accesses across the sync points.
+        auto bar = [] {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
         stencil_features(sR, feat[tid]);
         stencil_features(sL, feat[256 + tid]);
-        __syncthreads();
+        bar();
         const MlpOperands o = mlp_load(P, lane);
-        auto bar = [] { __syncthreads(); };
         for (int T = 0; T < 8; ++T) {
             const int base = (T >> 2) * 256 + wv * 64 + 16 * (T & 3);
             mlp_tile_forward(o, &feat[base], hid[wv], &zo[base], (float(*)[16][33]) nullptr, lane, bar);
@@ -268,21 +276,22 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
             if (eR <= A.theta) oR[r] = pR[r];
             if (eL <= A.theta) oL[r] = pL[r];
         }
-        // per-block statistics: proposals judged, fallbacks, summed judged error
-        red[0][tid] = nfall;
-        red[1][tid] = err_sum;
-        __syncthreads();
-        for (int sft = 128; sft > 0; sft >>= 1) {
-            if (tid < sft) {
-                red[0][tid] += red[0][tid + sft];
-                red[1][tid] += red[1][tid + sft];
-            }
-            __syncthreads();
+        // per-block statistics: proposals judged, fallbacks, summed judged error (sums within each
+        // wave by shuffles, then across the four waves)
+#pragma unroll
+        for (int sft = 32; sft > 0; sft >>= 1) {
+            nfall += __shfl_down(nfall, sft, 64);
+            err_sum += __shfl_down(err_sum, sft, 64);
         }
+        if (lane == 0) {
+            red[0][wv] = nfall;
+            red[1][wv] = err_sum;
+        }
+        __syncthreads();
         if (tid == 0) {
             const int64_t nb = blockIdx.x;
-            stats[3 * nb + 0] = red[0][0];
-            stats[3 * nb + 1] = red[1][0];
+            stats[3 * nb + 0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+            stats[3 * nb + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
             stats[3 * nb + 2] = (double)(((int64_t)A.nx * A.ny - (int64_t)blockIdx.x * 256) < 256
                                              ? 2 * ((int64_t)A.nx * A.ny - (int64_t)blockIdx.x * 256)
                                              : 512);
