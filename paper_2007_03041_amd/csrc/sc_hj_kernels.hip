@@ -22,12 +22,11 @@ namespace scx {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// float -> bfloat16 bits, round to nearest even (finite inputs)
+// float -> bfloat16 bits, round to nearest even: the gfx950 conversion instruction (two values per
+// instruction where the compiler pairs them)
 __device__ __forceinline__ short f2bf(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+    return __builtin_bit_cast(short, (__bf16)x);
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
