@@ -33,16 +33,18 @@ extern size_t g_pool_used;
 template <typename F>
 hipError_t timed(const char *fallback_name, hipStream_t st, F &&launch)
 {
-    bool on = g_timing;
-    if (on && !g_timing_only.empty()) {
-        on = false;
-        for (const auto &s : g_timing_only) on = on || s == fallback_name;
-    }
-    if (!on) {
+    if (!g_timing) {
         const char *nm = fallback_name;
         return launch(&nm);
     }
-    std::lock_guard<std::mutex> lk(g_tmu);
+    std::unique_lock<std::mutex> lk(g_tmu);
+    bool selected = g_timing_only.empty();
+    for (const auto &s : g_timing_only) selected = selected || s == fallback_name;
+    if (!selected) {
+        lk.unlock();
+        const char *nm = fallback_name;
+        return launch(&nm);
+    }
     if (g_pool_used == g_pool.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;

@@ -101,3 +101,18 @@ def test_batch_validation_before_device_use():
     arr = (sc.sc_batch_item * 1)()
     assert lib.sc_batch_plan_create(arr, 0, sc.SC_F64, 6, ctypes.byref(ctypes.c_void_p())) == sc.SC_ERR_ARG
     assert lib.sc_batch_plan_create(arr, 1, sc.SC_F64, 5, ctypes.byref(ctypes.c_void_p())) == sc.SC_ERR_UNSUPPORTED
+
+
+def test_timing_select_parses_and_validates():
+    """sc_timing_select: comma-separated names (empty entries ignored), NULL or "" clears the
+    selection, lists over 1023 bytes are rejected; nothing touches the device and no launch is timed
+    while timing is off."""
+    lib = sc.load()
+    assert lib.sc_timing_select(b"line_pass_fused_x,,line_pass_apply_yz,") == sc.SC_OK
+    assert lib.sc_timing_select(None) == sc.SC_OK
+    assert lib.sc_timing_select(b"") == sc.SC_OK
+    assert lib.sc_timing_select(b"x" * 1024) == sc.SC_ERR_ARG
+    assert "1023" in lib.sc_last_error().decode()
+    sc.timing_select(["line_pass_agg_yz"])
+    sc.timing_select(None)
+    assert sc.timing_read() == {}
