@@ -379,37 +379,67 @@ __global__ void __launch_bounds__(256) hj_init_speed(const double *__restrict__ 
 
 // One block: reduce the per-block maxima (and the proposer statistics), then advance the state.
 // mode 0: initialise (c = max, t = 0, counters = 0); mode 1: after an update (t += dt with the old c,
-// then c = max).
-__global__ void __launch_bounds__(256) hj_finish_step(const double *__restrict__ part, int64_t nparts,
-                                                      const double *__restrict__ stats, int64_t nstats,
-                                                      const HjStepArgs A, double *__restrict__ state, int mode)
+// then c = max).  1024 threads with four independent loads in flight each, so the reduction of the
+// per-block partials is not one latency-bound walk; wave shuffles, then one exchange across waves.
+constexpr int HJ_FIN_THREADS = 1024;
+__device__ __forceinline__ double wave_max(double v)
 {
-    __shared__ double red[4][256];
-    const int tid = threadIdx.x;
-    double m = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t i = tid; i < nparts; i += 256) m = fmax(m, part[i]);
-    for (int64_t i = tid; i < nstats; i += 256) {
-        s0 += stats[3 * i + 0];
-        s1 += stats[3 * i + 1];
-        s2 += stats[3 * i + 2];
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = fmax(v, __shfl_down(v, s, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+    return v;
+}
+__global__ void __launch_bounds__(HJ_FIN_THREADS) hj_finish_step(const double *__restrict__ part, int64_t nparts,
+                                                                 const double *__restrict__ stats, int64_t nstats,
+                                                                 const HjStepArgs A, double *__restrict__ state,
+                                                                 int mode)
+{
+    constexpr int NT = HJ_FIN_THREADS, U = 4;
+    __shared__ double red[4][NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double mu[U] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < nparts; i += U * NT) {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (i + k * NT < nparts) mu[k] = fmax(mu[k], part[i + k * NT]);
     }
-    red[0][tid] = m;
-    red[1][tid] = s0;
-    red[2][tid] = s1;
-    red[3][tid] = s2;
+    double s0[U] = {0.0, 0.0, 0.0, 0.0}, s1[U] = {0.0, 0.0, 0.0, 0.0}, s2[U] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < nstats; i += U * NT) {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (i + k * NT < nstats) {
+                const double *q = stats + 3 * (i + k * NT);
+                s0[k] += q[0];
+                s1[k] += q[1];
+                s2[k] += q[2];
+            }
+    }
+    const double m = wave_max(fmax(fmax(mu[0], mu[1]), fmax(mu[2], mu[3])));
+    const double t0 = wave_sum((s0[0] + s0[1]) + (s0[2] + s0[3]));
+    const double t1 = wave_sum((s1[0] + s1[1]) + (s1[2] + s1[3]));
+    const double t2 = wave_sum((s2[0] + s2[1]) + (s2[2] + s2[3]));
+    if (lane == 0) {
+        red[0][wv] = m;
+        red[1][wv] = t0;
+        red[2][wv] = t1;
+        red[3][wv] = t2;
+    }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            red[0][tid] = fmax(red[0][tid], red[0][tid + s]);
-            red[1][tid] += red[1][tid + s];
-            red[2][tid] += red[2][tid + s];
-            red[3][tid] += red[3][tid + s];
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
+        double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+            M = fmax(M, red[0][w]);
+            S0 += red[1][w];
+            S1 += red[2][w];
+            S2 += red[3][w];
+        }
         if (mode == 0) {
-            state[HJ_S_C] = red[0][0];
+            state[HJ_S_C] = M;
             state[HJ_S_T] = 0.0;
             state[HJ_S_STEPS] = 0.0;
             state[HJ_S_FALLBACK] = 0.0;
@@ -421,10 +451,10 @@ __global__ void __launch_bounds__(256) hj_finish_step(const double *__restrict__
             if (dt > 0.0) {
                 state[HJ_S_T] += dt;
                 state[HJ_S_STEPS] += 1.0;
-                state[HJ_S_C] = red[0][0];
-                state[HJ_S_FALLBACK] += red[1][0];
-                state[HJ_S_ERRSUM] += red[2][0];
-                state[HJ_S_JUDGED] += red[3][0];
+                state[HJ_S_C] = M;
+                state[HJ_S_FALLBACK] += S0;
+                state[HJ_S_ERRSUM] += S1;
+                state[HJ_S_JUDGED] += S2;
             }
         }
     }
@@ -781,7 +811,7 @@ hipError_t launch_hj_init_speed(const double *u, const HjStepArgs &A, double *pa
 hipError_t launch_hj_finish(const double *part, int64_t nparts, const double *stats, int64_t nstats,
                             const HjStepArgs &A, double *state, int mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(hj_finish_step, dim3(1), dim3(256), 0, st, part, nparts, stats, nstats, A, state, mode);
+    hipLaunchKernelGGL(hj_finish_step, dim3(1), dim3(HJ_FIN_THREADS), 0, st, part, nparts, stats, nstats, A, state, mode);
     return hipGetLastError();
 }
 
