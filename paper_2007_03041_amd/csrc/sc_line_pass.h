@@ -472,6 +472,42 @@ __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)]
             }
             vals[k] = ok ? ldg(rowp + k * NT + dp) : T(0);
         }
+    } else if (CONTIG && FULL && NT >= ORDER * TC) {
+        // full multi-line x tiles: thread tid serves line tid / TPL, points q = tid % TPL + k TPL of
+        // it (TPL = NT / TC threads per line, coalesced along the line); the middle groups lie inside
+        // the line.  A thread whose line does not exist reads line 0 instead (its results are never
+        // stored), so no load depends on a per-lane condition.
+        constexpr int TPL = NT / TC;
+        const int cc = tid / TPL;
+        const int q0 = tid % TPL;
+        const int64_t lbase_c = (line0 + cc < a.nlines) ? lb[cc] : lb[0];
+        const T *rowp = v + lbase_c + ((int)cstart - H + q0);
+#pragma unroll
+        for (int k = 0; k < FILL; ++k) {
+            const int q = q0 + k * TPL;
+            if (k > 0 && k < FILL - 1) {
+                vals[k] = ldg(rowp + k * TPL);
+                continue;
+            }
+            const int p = (int)cstart - H + q;
+            bool ok = q < W;
+            int dp = 0;
+            if (p < 0 || p >= ni) {
+                if (a.bc == 0) {
+                    int pw = p;
+                    if (wrap_many) {
+                        pw %= ni;
+                        if (pw < 0) pw += ni;
+                    } else {
+                        pw = p < 0 ? p + ni : p - ni;
+                    }
+                    dp = pw - p;
+                } else {
+                    ok = false;
+                }
+            }
+            vals[k] = ok ? ldg(rowp + k * TPL + dp) : T(0);
+        }
     } else if (!CONTIG && (int)cstart - H >= 0 && (int)cstart - H + W <= ni) {
         // strided tile inside its lines: thread tid loads line tid % TC, rows tid / TC + k NT / TC
         const int cc = tid % TC;

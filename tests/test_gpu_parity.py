@@ -67,7 +67,7 @@ def test_config1_replicated_lines(gpu_lib):
 # ------------------------------------------------------------------------------ ragged 1-D lines
 CASES = []
 _r = np.random.default_rng(5)
-for n in (7, 9, 64, 100, 129, 511, 513, 1000, 2048, 2049, 4096, 4097, 9000, 16384):
+for n in (7, 9, 64, 100, 129, 256, 511, 512, 513, 1000, 1024, 2048, 2049, 4096, 4097, 9000, 16384):
     for bc in ("periodic", "dirichlet"):
         for order in (4, 6):
             CASES.append((n, bc, order, float(10 ** _r.uniform(-2, math.log10(20)))))
