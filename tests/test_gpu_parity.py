@@ -138,6 +138,30 @@ def test_lines_of_many_chunks(gpu_lib, bc):
         assert err(got, ref, np.abs(v).max()) < TOL, op
 
 
+STRIDED_CHUNKED = [(4096, "periodic", 4), (4096, "dirichlet", 6), (4608, "dirichlet", 4), (4608, "periodic", 6),
+                   (17408, "periodic", 4), (17408, "dirichlet", 6)]
+
+
+@pytest.mark.parametrize("n,bc,order", STRIDED_CHUNKED)
+def test_strided_chunked_full_lines(gpu_lib, n, bc, order):
+    """y lines that are whole numbers of chunks: 8 chunks (carries formed in the apply launch from
+    prefetched chunk totals), 9 chunks (from the totals read in the carry step) and 17 chunks (the
+    carry launch), periodic and Dirichlet, against the oracle."""
+    sc = gpu_lib
+    cols = 16
+    v = W.random_field((n, cols), index=90 + n)
+    g = Grid((cols, n), (0.0, 0.0), (1.0, 3.0), ("periodic", bc))
+    alpha = 0.05 / g.dx(1)
+    gv = np.random.default_rng(n + 3).standard_normal((cols, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), 1, op, order, alpha, 1, 1.0, v, gv)
+        got = host(sc.apply_D_partial_sum(dev(v), g, 1, op, order, alpha, 1, 1.0, g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(v).max()) < TOL, op
+        ref = oracle.apply_invL(ogrid(g), 1, op, order, alpha, v, gv)
+        got = host(sc.apply_invL(dev(v), g, 1, op, order, alpha, g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+
+
 # ------------------------------------------------------------------------------ strided axes
 SHAPES = [
     ((41, 37, 5), ("periodic", "dirichlet", "periodic")),
