@@ -575,11 +575,21 @@ struct Ptrs {
     const double *carry;
 };
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (block b on XCD b mod 8).  The apply
+// tiles of one line group read the same chunk totals; numbering the logical tiles XCD by XCD keeps a
+// line group's chunks on one XCD, so those totals come from its L2 once.
+__device__ __forceinline__ int64_t xcd_grouped(int64_t b, int64_t nblocks)
+{
+    constexpr int64_t NX = 8;
+    const int64_t whole = (nblocks / NX) * NX;
+    return b < whole ? (b % NX) * (whole / NX) + b / NX : b;
+}
+
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI, bool FULL>
 __global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
 {
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int tid_in = threadIdx.x;
 #include "sc_line_pass_body.inc"
 }
