@@ -92,6 +92,20 @@ sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, doubl
                         const double *dirichlet_g, const void *v, void *out, void *ws,
                         size_t ws_bytes, sc_stream_t stream);
 
+/* sc_apply_invL for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same operation, arguments and errors
+ * as sc_apply_invL, without a workspace.  The per-(line, chunk) sweep totals and carries of
+ * chunked passes go to a fixed scratch array of SC_NOALLOC_SCRATCH_BYTES in the library's device
+ * image, one per GPU, held until the process ends; a pass that needs more (sc_workspace_bytes
+ * with which = 0, less its 256 bytes of alignment slack) fails with SC_ERR_WORKSPACE before
+ * anything is enqueued.  The call allocates nothing.  It uses the copy of the current device (the
+ * stream must belong to it).  All calls on one GPU share that array: calls that overlap in time on
+ * one GPU (different streams, or threads) race and give wrong results; calls ordered on one stream
+ * are safe, each writes every entry it reads. */
+#define SC_NOALLOC_SCRATCH_BYTES (8u << 20)
+sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+                                const double *dirichlet_g, const void *v, void *out, sc_stream_t stream);
+
 /* out = scale * sum_{p=1..k} D^p[v], D = I - L_op^{-1} (Sec. 2.2, successive relation), k in 1..8.
  * scale = +alpha, -alpha, -alpha^2 gives the left-biased, right-biased and second derivative
  * representations.  Dirichlet axes support k = 1 only (SC_ERR_UNSUPPORTED otherwise). */

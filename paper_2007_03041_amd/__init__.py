@@ -33,7 +33,10 @@ SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_
            "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_workspace_bytes",
            "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
            "sc_batch_describe", "sc_hj_workspace_bytes", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
-           "sc_mlp_param_count", "sc_mlp_forward", "sc_mlp_grad_workspace_bytes", "sc_mlp_grad", "sc_mlp_adam")
+           "sc_mlp_param_count", "sc_mlp_forward", "sc_mlp_grad_workspace_bytes", "sc_mlp_grad", "sc_mlp_adam",
+           "sc_apply_invL_noalloc")
+# fixed scratch of sc_apply_invL_noalloc (SC_NOALLOC_SCRATCH_BYTES in include/sc.h)
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class ScError(RuntimeError):
@@ -114,6 +117,7 @@ def load():
                                 c_void_p]
     lib.sc_apply_invL.argtypes = [gp, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_size_t, c_void_p]
+    lib.sc_apply_invL_noalloc.argtypes = [gp, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.sc_apply_D_partial_sum.argtypes = [gp, c_int, c_int, c_int, c_double, c_int, c_double, c_void_p,
                                            c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.sc_time_step.argtypes = [gp, POINTER(sc_linear_pde), c_int, c_void_p, c_void_p, c_size_t, c_void_p]
@@ -155,7 +159,8 @@ def load():
     lib.sc_mlp_grad.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]
     lib.sc_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]
-    for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_sum", "sc_time_step",
+    for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_invL_noalloc", "sc_apply_D_partial_sum",
+              "sc_time_step",
               "sc_timing_enable", "sc_timing_select", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
               "sc_batch_apply_per_instance", "sc_batch_tune", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
               "sc_mlp_forward", "sc_mlp_grad", "sc_mlp_adam"):
@@ -263,6 +268,22 @@ def apply_invL(v, grid: Grid, dim: int, op: str, order: int, alpha: float, g=Non
     nbytes = 0 if ws is None else ws.numel() - 256
     _check(lib.sc_apply_invL(ctypes.byref(gc), dim, OPS[op], order, alpha, _gptr(g, grid, dim), v.data_ptr(),
                              out.data_ptr(), wsp, nbytes, _stream()))
+    return out
+
+
+def apply_invL_noalloc(v, grid: Grid, dim: int, op: str, order: int, alpha: float, g=None, out=None):
+    """out = L_op^{-1}[v] along ``dim`` through ``sc_apply_invL_noalloc`` (no workspace: the
+    library's fixed per-GPU scratch holds the chunk totals).  ``out`` must be given by callers that
+    cannot allocate."""
+    import torch
+
+    lib = load()
+    _tensor_ok(v, grid, "v")
+    out = torch.empty_like(v) if out is None else out
+    _tensor_ok(out, grid, "out")
+    gc = grid.c()
+    _check(lib.sc_apply_invL_noalloc(ctypes.byref(gc), dim, OPS[op], order, alpha, _gptr(g, grid, dim),
+                                     v.data_ptr(), out.data_ptr(), _stream()))
     return out
 
 

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libsc.so")
 # the line-pass units first: they take longest
 SOURCES = ["sc_lp_f64_o4.hip", "sc_lp_f64_o6.hip", "sc_lp_f32_o4.hip", "sc_lp_f32_o6.hip", "sc_lp_f64_o4_full.hip",
            "sc_lp_f64_o6_full.hip", "sc_lp_f32_o4_full.hip", "sc_lp_f32_o6_full.hip", "sc_api.cpp", "sc_batch.cpp",
-           "sc_coeffs.cpp", "sc_hj.cpp", "sc_hj_kernels.hip", "sc_kernels.hip"]
+           "sc_coeffs.cpp", "sc_hj.cpp", "sc_hj_kernels.hip", "sc_kernels.hip", "sc_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

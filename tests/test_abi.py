@@ -116,3 +116,19 @@ def test_timing_select_parses_and_validates():
     sc.timing_select(["line_pass_agg_yz"])
     sc.timing_select(None)
     assert sc.timing_read() == {}
+
+
+def test_noalloc_entry_point_refuses_passes_beyond_its_scratch():
+    """sc_apply_invL_noalloc validates like sc_apply_invL and refuses, before anything is enqueued,
+    a pass whose chunk totals need more than the fixed scratch."""
+    lib = sc.load()
+    g = sc.Grid((16384, 16384))
+    gc = g.c()
+    assert sc.workspace_bytes(g, 1, 0) - 256 > sc.NOALLOC_SCRATCH_BYTES
+    rc = lib.sc_apply_invL_noalloc(ctypes.byref(gc), 1, 2, 6, 100.0, None, 0x1000, 0x100000000000, None)
+    assert rc == sc.SC_ERR_WORKSPACE
+    assert "scratch" in lib.sc_last_error().decode()
+    assert lib.sc_apply_invL_noalloc(ctypes.byref(gc), 1, 2, 5, 100.0, None, 0x1000, 0x100000000000,
+                                     None) == sc.SC_ERR_UNSUPPORTED
+    assert lib.sc_apply_invL_noalloc(ctypes.byref(gc), 1, 2, 6, -1.0, None, 0x1000, 0x100000000000,
+                                     None) == sc.SC_ERR_ARG
