@@ -79,9 +79,11 @@ def loss(om, target) -> float:
     return float(((om - target) ** 2).sum(axis=-1).mean())
 
 
-def backward(p, cache, target, emulate_bf16: bool = False):
+def backward(p, cache, target, emulate_bf16: bool = False, with_upstream: bool = False):
     """Gradients of ``loss`` w.r.t. every parameter (chain rule written out layer by layer).  With
-    emulate_bf16 the upstream gradients entering matrix products are BF16-rounded too."""
+    emulate_bf16 the upstream gradients entering matrix products are BF16-rounded too.  With
+    with_upstream, also returns the gradients w.r.t. the pre-activations (z3, z2, z1) as they enter
+    the products (for error bounds in tests)."""
     r = bf16 if emulate_bf16 else (lambda a: a)
     n = target.shape[0]
     om = cache["om"]
@@ -101,7 +103,10 @@ def backward(p, cache, target, emulate_bf16: bool = False):
     g1r = r(g_z1)
     gW1 = g1r.T @ cache["x0"]
     gb1 = g_z1.sum(axis=0)
-    return dict(W1=gW1, b1=gb1, W2=gW2, b2=gb2, W3=gW3, b3=gb3)
+    grads = dict(W1=gW1, b1=gb1, W2=gW2, b2=gb2, W3=gW3, b3=gb3)
+    if with_upstream:
+        return grads, dict(z3=g3r, z2=g2r, z1=g1r)
+    return grads
 
 
 def adam_step(p, g, state, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):

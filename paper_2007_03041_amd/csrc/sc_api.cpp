@@ -42,6 +42,9 @@ sc_status fail(sc_status s, const std::string &msg)
 // grid helpers
 // ------------------------------------------------------------------------------------------
 
+// Tile index arithmetic along a line is 32-bit (a chunk start plus a halo and a thread offset).
+constexpr int64_t kMaxLine = (int64_t(1) << 31) - 65536;
+
 sc_status check_grid(const sc_grid *g)
 {
     if (!g) return fail(SC_ERR_ARG, "grid is NULL");
@@ -50,6 +53,7 @@ sc_status check_grid(const sc_grid *g)
     int64_t total = 1;
     for (int e = 0; e < g->ndim; ++e) {
         if (g->n[e] < 1) return fail(SC_ERR_SHAPE, "n must be >= 1 on every axis");
+        if (g->n[e] > kMaxLine) return fail(SC_ERR_SHAPE, "more than 2^31 - 2^16 points on one axis");
         if (g->bc[e] != SC_BC_PERIODIC && g->bc[e] != SC_BC_DIRICHLET) return fail(SC_ERR_ARG, "unknown bc");
         if (!(g->hi[e] > g->lo[e]) || !std::isfinite(g->hi[e] - g->lo[e]))
             return fail(SC_ERR_ARG, "each axis needs lo < hi");

@@ -289,6 +289,8 @@ sc_status sc_batch_plan_create(const sc_batch_item *items, int count, int dtype,
         if (it.n < order + 1) return fail(SC_ERR_SHAPE, std::string(where) + "line shorter than the stencil");
         if (it.nlines < 1 || it.offset < 0) return fail(SC_ERR_SHAPE, std::string(where) + "bad line count or offset");
         if (it.n > (int64_t(1) << 40) / it.nlines) return fail(SC_ERR_SHAPE, std::string(where) + "too large");
+        // tile index arithmetic along a line is 32-bit
+        if (it.n > (int64_t(1) << 31) - 65536) return fail(SC_ERR_SHAPE, std::string(where) + "line longer than 2^31 - 2^16");
         if (it.bc != SC_BC_PERIODIC && it.bc != SC_BC_DIRICHLET) return fail(SC_ERR_ARG, std::string(where) + "unknown bc");
         if (it.op < SC_OP_L || it.op > SC_OP_0) return fail(SC_ERR_ARG, std::string(where) + "unknown op");
         if (it.k != 0 && it.k != 1) return fail(SC_ERR_UNSUPPORTED, std::string(where) + "batches take k = 0 or 1");

@@ -132,3 +132,29 @@ def test_noalloc_entry_point_refuses_passes_beyond_its_scratch():
                                      None) == sc.SC_ERR_UNSUPPORTED
     assert lib.sc_apply_invL_noalloc(ctypes.byref(gc), 1, 2, 6, -1.0, None, 0x1000, 0x100000000000,
                                      None) == sc.SC_ERR_ARG
+
+
+def test_lines_beyond_32_bit_tile_indexing_are_refused():
+    """Tile index arithmetic along a line is 32-bit: a line of 2^31 - 2^16 points or more is refused
+    with SC_ERR_SHAPE before anything is enqueued (every entry point, and batch instances)."""
+    lib = sc.load()
+    n = 2 ** 31
+    g = sc.Grid((n,))
+    assert _call_invL(g, v=0x1000, out=0x1000 + 16 * n) == sc.SC_ERR_SHAPE
+    assert "2^31" in lib.sc_last_error().decode()
+    gc = sc.Grid((4, n)).c()
+    rc = lib.sc_apply_D_partial_sum(ctypes.byref(gc), 1, 2, 6, 10.0, 1, 1.0, None, 0x1000, 0x1000 + 64 * n,
+                                    None, 0, None)
+    assert rc == sc.SC_ERR_SHAPE
+    rc = lib.sc_apply_invL_noalloc(ctypes.byref(gc), 1, 2, 6, 10.0, None, 0x1000, 0x1000 + 64 * n, None)
+    assert rc == sc.SC_ERR_SHAPE
+    # the largest accepted length passes validation (it then fails on the missing workspace)
+    ok = sc.Grid((2 ** 31 - 2 ** 16,))
+    assert _call_invL(ok, v=0x1000, out=0x1000 + 16 * n) == sc.SC_ERR_WORKSPACE
+    arr = (sc.sc_batch_item * 1)()
+    for k, v in dict(offset=0, n=n, nlines=1, lo=0.0, hi=1.0, alpha=5e9, scale=1.0, g_offset=-1, bc=0, op=2,
+                     k=0).items():
+        setattr(arr[0], k, v)
+    h = ctypes.c_void_p()
+    assert lib.sc_batch_plan_create(arr, 1, sc.SC_F64, 6, ctypes.byref(h)) == sc.SC_ERR_SHAPE
+    assert not h.value

@@ -209,6 +209,42 @@ def test_mlp_gradients_match_central_differences():
             assert abs(fd - g[k][ix]) < 1e-7 + 1e-5 * abs(fd), (k, ix, fd, g[k][ix])
 
 
+def _adam_scalar(p0, grads, lr, **kw):
+    p = {"w": np.array([p0], dtype=float)}
+    st = {}
+    for g in grads:
+        mlp.adam_step(p, {"w": np.array([g], dtype=float)}, st, lr, **kw)
+    return float(p["w"][0]), st
+
+
+def test_adam_step_pinned_by_hand_derived_values():
+    """Adam (Kingma & Ba) at b1 = 0.9, b2 = 0.999, eps = 1e-8, values worked out by hand:
+    * step 1 from zero moments: m = 0.1 g, v = 0.001 g^2, the bias corrections give m^ = g,
+      v^ = g^2, so the parameter moves by -lr g / (|g| + eps);
+    * a constant gradient keeps m^ = g and v^ = g^2 at every step (the corrections divide by
+      1 - b^t exactly what the moments lack), so each step moves by the same amount;
+    * g = 1 then g = -1: m^ = (0.9 - 1) / 1.9 = -1/19, v^ = (0.999 + 1) / 1.999 = 1, so the second
+      step moves by +lr / (19 (1 + eps));
+    * a gradient of the size of eps: step 1 moves by -lr g / (g + eps) = -lr / 2 at g = eps
+      (eps outside the square root).
+    A dropped or misplaced bias correction, a swapped b1/b2 or eps inside the root fails one."""
+    lr, eps = 0.1, 1e-8
+    for g in (3.0, -0.25, 1e4):
+        w, st = _adam_scalar(0.5, [g], lr)
+        assert abs(w - (0.5 - lr * g / (abs(g) + eps))) < 1e-15
+        assert st["t"] == 1
+        assert abs(st["m_w"][0] - 0.1 * g) < 1e-15 * abs(g) and abs(st["v_w"][0] - 1e-3 * g * g) < 1e-15 * g * g
+    w, st = _adam_scalar(0.0, [2.0] * 5, lr)
+    assert abs(w - (-5 * lr * 2.0 / (2.0 + eps))) < 1e-14 and st["t"] == 5
+    w, _ = _adam_scalar(0.0, [1.0, -1.0], lr)
+    assert abs(w - (-lr / (1 + eps) + lr / (19 * (1 + eps)))) < 1e-15
+    w, _ = _adam_scalar(0.0, [eps], lr)
+    assert abs(w - (-lr / 2)) < 1e-15
+    # without the bias corrections step 1 would move by lr 0.1 / sqrt(0.001) = 3.16 lr: the pin above
+    # is a factor 3 away from that mistake
+    assert abs(0.1 / math.sqrt(1e-3) - 1.0) > 2
+
+
 def test_adam_decreases_the_loss_on_a_fixed_batch():
     r = np.random.default_rng(2)
     p = mlp.init_params(3)
