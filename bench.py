@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the successive-convolution hot path on one MI355X.
 
-Workload: 2-D linear advection-diffusion u_t + u_x + u_y = lap u on [0, 2 pi]^2, 4096 x 4096,
-periodic, FP64, fourth-order local quadrature, dimension-split x then y, dt = dx, beta = 1; initial
-data 8 seeded random Fourier modes (|k| <= 16, amplitudes U(-1, 1)).  One "step" is one time step:
-an x pass applying D_R and D_0 to every x line and a y pass applying them to every y line
-(4 one-dimensional operator applications per DOF).
+Headline workload: the 3-D heat equation u_t = lap u on [0, 1]^3, 512^3 points including the
+boundaries, homogeneous Dirichlet ends, FP64, sixth-order local quadrature, dt = dx, beta = 1,
+dimension-split: one "step" is an x, a y and a z pass, each u <- u - D_0[u] along every line of that
+axis (3 one-dimensional operator applications per DOF).  Initial data: 16 seeded Gaussian bumps.
+At 1.07 GB per field the working set is four times the 256 MB Infinity Cache.
 
-Prints one JSON line.  ``value`` = DOF x operator applications / s (the per-application update
-rate); ``paper_metric_dof_per_s`` = DOF / (time per step), the paper's DOF/node/s with one GPU as
+Prints one JSON line.  ``value`` = DOF x operator applications / s (each pass applies one operator);
+``config.paper_metric_dof_per_s`` = DOF / (time per step), the paper's DOF/node/s with one GPU as
 the node.  ``roofline`` reports the dominant kernel's algorithmic HBM bytes (16 B per DOF: read the
-operand, write the result) over its mean duration measured with HIP events recorded by the library
-on the launch stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample on the host cores
-and reports the GPU result's error against it.
+operand once, write the result once) over its mean launch duration, measured with HIP events that
+the library records on the launch stream inside the timed steps; ``per_pass`` and ``step`` give the
+same ratio per axis pass (all its launches) and per step.  ``traffic`` is FETCH_SIZE + WRITE_SIZE
+from the committed rocprofv3 counter summaries when they were taken on the current kernel sources.
+``cpu_baseline`` times the FP64 oracle on a bounded sample of the same workload on the host cores.
+``beside`` holds the other workloads measured the same way: the same heat step on the mixed
+FP32/FP64 path, the 2-D advection-diffusion step (4096^2), the 1-D line workload replicated to
+2^18 lines, the ragged batch, the Hamilton-Jacobi solver with classical and learned weights, and a
+plain device copy.
+
+``--only LEG`` runs one leg (for profiling): heat3d_f64, heat3d_mixed, advdiff2d, line1d, batch, hj,
+copy.
 """
 from __future__ import annotations
 
@@ -21,6 +30,9 @@ import hashlib
 import json
 import math
 import os
+import platform
+import statistics
+import subprocess
 import sys
 import time
 
@@ -28,25 +40,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-N = 4096
-ORDER = 4
-OPS_PER_STEP = 4
-BYTES_PER_DOF_PASS = 16
-NFIELDS = 4  # rotate independent fields so one pass never re-reads what the last few wrote
+METRIC = "DOF updates/s per L^{-1}/D application on 1 GPU; % HBM roofline; error vs FP64"
+HEAT_N = 512
+ADV_N = 4096
+LINE_N, LINE_LINES = 1024, 1 << 18
+NFIELDS = 4  # 2-D leg: rotate independent fields (134 MB each) so a pass never re-reads from cache
 
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2007_03041_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".inc")):
+        if f.endswith((".hip", ".h", ".inc", ".cpp")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries (None if stale or absent)."""
+def load_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summaries (None if stale or absent)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -54,85 +66,187 @@ def load_traffic(kernel: str):
         rec = json.load(f)
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    return k.get("hbm_bytes_per_launch")
+    k = rec.get("workloads", {}).get(workload, {}).get(kernel)
+    return None if not k else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, torch, grid, pde_kw):
-    """The FP64 oracle on a bounded sample (2 full-size steps from the benchmark's initial data),
-    timed on the host cores; the GPU runs the same 2 steps and its error against the oracle is
-    reported relative to max|u|."""
-    import numpy as np
+# ------------------------------------------------------------------------------------------------
+# timing
+# ------------------------------------------------------------------------------------------------
+def measure(sc, torch, step_fn, steps, warmup, profile_steps=3):
+    """Times `steps` calls of step_fn after `warmup` untimed ones.
 
-    import oracle
-    from paper_2007_03041_amd import workloads as W
-
-    steps = 2
-    u0 = W.fourier_field(N, N)
-    og = oracle.make_grid((N, N), (0.0, 0.0), (2 * math.pi, 2 * math.pi))
-    t0 = time.perf_counter()
-    ref = oracle.time_step(og, (1.0, 1.0), 1.0, 1.0, pde_kw["dt"], ORDER, steps, u0, split=True)
-    t = time.perf_counter() - t0
-    u = torch.from_numpy(u0).to("cuda")
-    sc.time_step(u, grid, steps, **pde_kw)
+    A short pass first times every launch of the library (HIP events on the launch stream) for the
+    per-kernel breakdown and to find the dominant kernel (largest total time per step).  In the timed
+    region only the dominant kernel's launches carry library events, and every step is bracketed by
+    a pair of events on the same stream for the per-step minimum and median.  Returns a dict."""
+    for _ in range(warmup):
+        step_fn()
     torch.cuda.synchronize()
-    err = float(np.abs(u.cpu().numpy() - ref).max() / np.abs(ref).max())
+    sc.timing_reset()
+    sc.timing_select(None)
+    sc.timing_enable(True)
+    for _ in range(profile_steps):
+        step_fn()
+    torch.cuda.synchronize()
+    sc.timing_enable(False)
+    breakdown = sc.timing_read()
+    sc.timing_reset()
+    dominant = max(breakdown.items(), key=lambda kv: kv[1][0])[0]
+    sc.timing_select([dominant])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    sc.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        step_fn()
+        b.record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    sc.timing_enable(False)
+    live = sc.timing_read()
+    sc.timing_reset()
+    sc.timing_select(None)
+    per_step = sorted(a.elapsed_time(b) for a, b in ev)
+    tot, cnt = live[dominant]
     return {
-        "value": N * N * OPS_PER_STEP * steps / t,
-        "unit": "DOF*applications/s",
-        "cores": oracle.num_threads(),
-        "kind": "oracle",
-        "sample": f"{steps} full-size time steps of the benchmark workload ({N}x{N}, FP64), "
-                  f"{t:.2f} s wall",
-        "gpu_max_rel_err_vs_oracle": err,
+        "total_s": total,
+        "ms_per_step": 1e3 * total / steps,
+        "step_ms_min": per_step[0],
+        "step_ms_median": statistics.median(per_step),
+        "dominant": dominant,
+        "dominant_mean_ms": tot / cnt,
+        "dominant_launches_per_step": cnt / steps,
+        "kernel_ms": {k: v[0] / v[1] for k, v in breakdown.items()},
+        "kernel_launches_per_step": {k: v[1] / profile_steps for k, v in breakdown.items()},
     }
 
 
-def heat3d_legs(sc, torch, reps=4):
-    """The 3-D heat workload (512^3 with both ends stored, Dirichlet 0, order 6, 5 dimension-split
-    steps u <- u - D_0 u along x, y, z, dt = dx, beta = 1, 16 seeded Gaussian bumps) on the FP64 path and on the
-    mixed path (FP32 data, compensated FP32 in-wave carries, FP64 cross-chunk carries and boundary
-    constants), timed side by side; the mixed result's error is taken against the FP64 GPU result
-    (the FP64 path itself matches the oracle to 1e-12 in the parity tests)."""
+def frac(bytes_, ms):
+    gbs = bytes_ / (ms / 1e3) / 1e9
+    return {"GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
+# ------------------------------------------------------------------------------------------------
+# workloads
+# ------------------------------------------------------------------------------------------------
+def heat3d(sc, torch, dtype_name, steps, warmup, n=HEAT_N):
+    """3-D heat workload, dimension-split; returns the leg's record and the final field."""
     import dataclasses
 
     from paper_2007_03041_amd import workloads as W
 
-    n, steps = 512, 5
     dx = 1.0 / (n - 1)
-    g64 = sc.Grid((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ("dirichlet",) * 3)
-    g32 = dataclasses.replace(g64, dtype=sc.SC_F32_MIXED)
+    g = sc.Grid((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ("dirichlet",) * 3)
+    tdt = torch.float64
+    if dtype_name == "mixed":
+        g = dataclasses.replace(g, dtype=sc.SC_F32_MIXED)
+        tdt = torch.float32
+    elem = 8 if tdt == torch.float64 else 4
     pde = sc.make_pde(nu_diff=1.0, beta=1.0, dt=dx, order=6, split=True)
-    u0 = W.bump_field(n, device="cuda")
-    out, res = {}, {}
-    for name, g, dt in (("f64", g64, torch.float64), ("mixed_f32", g32, torch.float32)):
-        st = sc.TimeStepper(g, pde)
-        u = u0.to(dt, copy=True)
-        st.step(u, steps)  # warm-up, and the result compared below
-        res[name] = u.to(torch.float64)
-        work = u0.to(dt, copy=True)
-        t, kname, kmean, kt = measure(sc, torch, lambda: st.step(work, steps), reps, profile_steps=1)
-        t /= reps * steps
-        elem = 8 if dt == torch.float64 else 4
-        kbytes = 2 * elem * n ** 3
-        out[name] = {
-            "dof_applications_per_s": n ** 3 * 3 / t,
-            "paper_metric_dof_per_s": n ** 3 / t,
-            "ms_per_step": 1e3 * t,
-            "bytes_per_dof_per_pass": 2 * elem,
-            "dominant_kernel": kname,
-            "dominant_kernel_GBps": kbytes / (kmean / 1e3) / 1e9,
-            "dominant_kernel_hbm_frac": kbytes / (kmean / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "kernel_ms": kt,
-        }
-        del st, u, work
-    d = (res["mixed_f32"] - res["f64"]).abs().max().item()
-    out["mixed_f32"]["max_rel_err_vs_f64_path"] = d / res["f64"].abs().max().item()
-    out["workload"] = ("3-D heat equation, 512^3 incl. boundaries, Dirichlet 0, order-6 quadrature, 5 "
-                       "dimension-split steps, dt=dx, beta=1, 16 seeded Gaussian bumps")
-    return out
+    st = sc.TimeStepper(g, pde)
+    u = W.bump_field(n, device="cuda").to(tdt)
+    m = measure(sc, torch, lambda: st.step(u, 1), steps, warmup)
+    dof = n ** 3
+    apps = 3
+    t_step = m["ms_per_step"] / 1e3
+    per_pass = {}
+    for axis in "xyz":
+        ms = sum(v * m["kernel_launches_per_step"][k] for k, v in m["kernel_ms"].items() if k.endswith("_" + axis))
+        per_pass[axis] = dict(ms=ms, **frac(2 * elem * dof, ms))
+    rec = {
+        "dof_applications_per_s": dof * apps / t_step,
+        "paper_metric_dof_per_s": dof / t_step,
+        "ms_per_step": m["ms_per_step"],
+        "step_ms_min": m["step_ms_min"],
+        "step_ms_median": m["step_ms_median"],
+        "bytes_per_dof_per_pass": 2 * elem,
+        "dominant_kernel": m["dominant"],
+        "dominant_mean_ms": m["dominant_mean_ms"],
+        "dominant": frac(2 * elem * dof, m["dominant_mean_ms"]),
+        "per_pass": per_pass,
+        "step": frac(3 * 2 * elem * dof, m["step_ms_median"]),
+        "kernel_ms": m["kernel_ms"],
+    }
+    return rec, m, u
+
+
+def advdiff2d(sc, torch, steps, warmup, n=ADV_N):
+    """2-D linear advection-diffusion u_t + u_x + u_y = lap u, 4096^2 periodic on [0, 2 pi]^2, FP64,
+    order 4, dimension-split x then y, dt = dx, beta = 1, 8 seeded Fourier modes: each pass applies
+    D_R and D_0 to the same operand (2 applications, 16 B/DOF)."""
+    from paper_2007_03041_amd import workloads as W
+
+    L = 2 * math.pi
+    g = sc.Grid((n, n), (0.0, 0.0), (L, L))
+    pde = sc.make_pde(c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=L / n, order=4, split=True)
+    st = sc.TimeStepper(g, pde)
+    fields = [W.fourier_field(n, n, device="cuda") for _ in range(NFIELDS)]
+    it = iter(range(1 << 62))
+    m = measure(sc, torch, lambda: st.step(fields[next(it) % NFIELDS], 1), steps, warmup)
+    dof = n * n
+    t = m["ms_per_step"] / 1e3
+    per_pass = {}
+    for axis in "xy":
+        ms = sum(v * m["kernel_launches_per_step"][k] for k, v in m["kernel_ms"].items() if k.endswith("_" + axis))
+        per_pass[axis] = dict(ms=ms, **frac(16 * dof, ms))
+    return {
+        "workload": "2-D linear advection-diffusion, 4096x4096 periodic on [0,2pi]^2, FP64, order-4 quadrature, "
+                    "dimension-split x then y, dt=dx, beta=1, 8 seeded Fourier modes, 4 fields rotated",
+        "dof_applications_per_s": dof * 4 / t,
+        "dof_passes_per_s": dof * 2 / t,
+        "paper_metric_dof_per_s": dof / t,
+        "ms_per_step": m["ms_per_step"],
+        "step_ms_min": m["step_ms_min"],
+        "step_ms_median": m["step_ms_median"],
+        "dominant_kernel": m["dominant"],
+        "dominant": frac(16 * dof, m["dominant_mean_ms"]),
+        "per_pass": per_pass,
+        "step": frac(32 * dof, m["step_ms_median"]),
+        "kernel_ms": m["kernel_ms"],
+    }
+
+
+def line1d(sc, torch, steps, warmup):
+    """The 1-D line workload (periodic [0, 1], N = 1024, alpha = 1024, sin(2 pi x) + 0.05 box-filtered
+    noise) replicated to 2^18 independent lines (2.1 GB): one L_0^{-1} and one fused S_3 = D + D^2 + D^3
+    per step, each reading the operand once and writing the result once."""
+    from paper_2007_03041_amd import workloads as W
+
+    g = sc.Grid((LINE_N, LINE_LINES), (0.0, 0.0), (1.0, 1.0))
+    base = torch.from_numpy(W.noisy_sine_line(LINE_N, index=1, lines=64)).to("cuda")
+    v = base.repeat(LINE_LINES // 64, 1).contiguous()
+    out = torch.empty_like(v)
+    res = {"workload": "1-D periodic line N=1024 on [0,1], alpha=1024 (nu=1), order 6, replicated to 2^18 lines, FP64"}
+    dof = LINE_N * LINE_LINES
+    for name, fn in (("invL_0", lambda: sc.apply_invL(v, g, 0, "0", 6, 1024.0, out=out)),
+                     ("S3_0", lambda: sc.apply_D_partial_sum(v, g, 0, "0", 6, 1024.0, 3, 1.0, out=out))):
+        m = measure(sc, torch, fn, steps, warmup)
+        res[name] = {"ms_min": m["step_ms_min"], "ms_median": m["step_ms_median"],
+                     "dof_per_s": dof / (m["step_ms_median"] / 1e3),
+                     "kernel": m["dominant"], "kernel_mean_ms": m["dominant_mean_ms"],
+                     **frac(16 * dof, m["step_ms_median"])}
+    return res
+
+
+def copy_leg(torch, nbytes=1 << 30, reps=20):
+    """A plain device-to-device copy of 1 GiB (torch copy_): the bandwidth a streaming kernel gets."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        dst.copy_(src)
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    med = statistics.median(ts)
+    return {"bytes_moved": 2 * nbytes, "ms_min": ts[0], "ms_median": med,
+            "GBps_median": 2 * nbytes / (med / 1e3) / 1e9, "GBps_best": 2 * nbytes / (ts[0] / 1e3) / 1e9,
+            "frac_of_peak_median": 2 * nbytes / (med / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
 def batch_legs(sc, torch, reps=5):
@@ -188,15 +302,14 @@ def hj_legs(sc, torch, n=2048, t_end=1.5, cfl=0.5, nsamples=1_000_000, train_ste
     """The nonlinear Hamilton-Jacobi workload (u_t + |grad u|^2 / 2 = 0, 2048^2 periodic on
     [0, 2 pi]^2, u0 = sin x + sin y, CFL 1/2 -- the 2-D Lax-Friedrichs bound dt (c/dx + c/dy) <= 1;
     at CFL 1 the wave speed grows after the kinks form at this resolution -- adaptive lagged step,
-    to t = 1.5 after the kinks form):
-    the proposer trained on the GPU on 1e6 stencils harvested from classical (WENO-Z) runs, then the
-    solver with linear, WENO-Z and learned weights timed side by side."""
+    to t = 1.5 after the kinks form): the proposer trained on the GPU on 1e6 stencils harvested from
+    classical (WENO-Z) runs, then the solver with linear, WENO-Z and learned weights timed side by
+    side."""
     L = 2 * math.pi
     x = torch.arange(n, dtype=torch.float64, device="cuda") * (L / n)
     u0 = torch.sin(x)[None, :] + torch.sin(x)[:, None]
     out = {"workload": f"H-J u_t + |grad u|^2/2 = 0, {n}x{n} periodic, u0 = sin x + sin y, CFL {cfl}, "
                        f"beta 1, to t = {t_end}"}
-    # training data: stencils of classical runs at four times, 1e6 drawn at random
     t0 = time.perf_counter()
     Xs, Ys = [], []
     for T in (0.25, 0.75, 1.25, 1.75):
@@ -232,7 +345,7 @@ def hj_legs(sc, torch, n=2048, t_end=1.5, cfl=0.5, nsamples=1_000_000, train_ste
     tr = sc.MlpTrainer(params, max_batch=batch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    first = last = None
+    first = None
     for k in range(train_steps):
         i1 = torch.randint(0, X.shape[0], (batch // 2,), device="cuda", generator=gen)
         i2 = rare[torch.randint(0, rare.numel(), (batch // 2,), device="cuda", generator=gen)]
@@ -286,56 +399,109 @@ def _linear_weights_from(sc, L, cfl):
     return Y[2 * 8].tolist()
 
 
-def calibrate_copy(torch, nbytes=1 << 30, reps=5):
-    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE readings."""
-    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"calibration_copy_bytes_each_way": nbytes, "reps": reps}))
+# ------------------------------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the headline workload
+# ------------------------------------------------------------------------------------------------
+def host_info():
+    info = {"nproc": os.cpu_count(), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz")
+        info["lscpu"] = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in out.splitlines() if ":" in l)
+                         if k.strip() in keep}
+    except Exception as e:  # lscpu missing: say so
+        info["lscpu"] = f"unavailable: {e}"
+    try:
+        info["nproc_cmd"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout)
+    except Exception:
+        pass
+    return info
 
 
-def measure(sc, torch, step_fn, steps, profile_steps=10):
-    """Times `steps` calls of step_fn.  A short pass first times every launch of the library (HIP
-    events on the launch stream) for the per-kernel breakdown and to find the dominant kernel; in
-    the measured region only the dominant kernel's launches carry events (each timed launch adds
-    two event records to the stream).  Returns (seconds, dominant kernel, its mean launch ms in the
-    measured region, {kernel: mean ms} of the breakdown pass)."""
-    torch.cuda.synchronize()
-    sc.timing_reset()
-    sc.timing_select(None)
-    sc.timing_enable(True)
-    for _ in range(profile_steps):
-        step_fn()
-    torch.cuda.synchronize()
-    sc.timing_enable(False)
-    breakdown = sc.timing_read()
-    sc.timing_reset()
-    dominant = max(breakdown.items(), key=lambda kv: kv[1][0])[0]
-    sc.timing_select([dominant])
-    sc.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step_fn()
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    sc.timing_enable(False)
-    live = sc.timing_read()
-    sc.timing_reset()
-    sc.timing_select(None)
-    tot, cnt = live[dominant]
-    return t, dominant, tot / cnt, {k: v[0] / v[1] for k, v in breakdown.items()}
+def cpu_baseline(sc, torch, reps=10, warm=3):
+    """The FP64 oracle on a bounded sample of the headline workload: the x, y and z passes of one
+    heat step (u <- u - D_0 u along one axis, order 6, Dirichlet, alpha = 1/sqrt(dx), dx = 1/511),
+    each over 128 full lines of 512 points (the per-line work of the 512^3 step).  Two builds --
+    the reference build every test checks (-O2 -ffp-contract=off) and a labelled -O3 -march=native
+    timing build -- on one thread and on all threads the process may use; `warm` untimed runs,
+    then `reps` timed runs, minimum and median.  The GPU applies the same passes to the same sample
+    arrays and its error against the oracle is reported."""
+    import numpy as np
+
+    import oracle
+    from paper_2007_03041_amd import workloads as W
+
+    n, lines = HEAT_N, 128
+    dx = 1.0 / (n - 1)
+    alpha = 1.0 / math.sqrt(dx)
+    # x lines: grid (512, 128); y/z lines: grid (128, 512) along its second axis (strided lines)
+    gx = oracle.make_grid((n, lines), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet"))
+    gy = oracle.make_grid((lines, n), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet"))
+    full = W.bump_field(n, device="cuda")                       # the headline's initial data
+    vx = full[n // 2, n // 2 - lines // 2:n // 2 + lines // 2, :].cpu().numpy().copy()  # 128 x lines
+    vy = full[n // 2, :, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # 128 y lines
+    vz = full[:, n // 2, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # 128 z lines
+    del full
+    cases = ((gx, 0, vx), (gy, 1, vy), (gy, 1, vz))
+    sample_dof_apps = 3 * n * lines
+
+    def run():
+        return [oracle.apply_D_partial_sum(g, d, "0", 6, alpha, 1, -1.0, v) for g, d, v in cases]
+
+    threads_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    timings = {}
+    ref_out = None
+    for build in ("reference", "native"):
+        oracle.use_build(build)
+        for nt in (1, threads_all):
+            used = oracle.set_threads(nt)
+            for _ in range(warm):
+                out = run()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                out = run()
+                ts.append(time.perf_counter() - t0)
+            if build == "reference" and ref_out is None:
+                ref_out = out
+            ts.sort()
+            timings[f"{build}_{used}t"] = {"threads": used, "s_min": ts[0], "s_median": statistics.median(ts),
+                                           "dof_applications_per_s_best": sample_dof_apps / ts[0],
+                                           "dof_applications_per_s_median": sample_dof_apps / statistics.median(ts)}
+    oracle.use_build("reference")
+    # the GPU on the same sample arrays
+    err = 0.0
+    grids = {0: sc.Grid((n, lines), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet")),
+             1: sc.Grid((lines, n), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet"))}
+    for (g, d, v), ref in zip(cases, ref_out):
+        got = sc.apply_D_partial_sum(torch.from_numpy(v).to("cuda"), grids[d], d, "0", 6, alpha, 1, -1.0)
+        err = max(err, float(np.abs(got.cpu().numpy() - ref).max() / np.abs(v).max()))
+    best_all = timings[f"reference_{threads_all}t"] if f"reference_{threads_all}t" in timings else None
+    head = best_all or max(timings.values(), key=lambda r: r["threads"])
+    return {
+        "value": head["dof_applications_per_s_median"],
+        "unit": "DOF*applications/s",
+        "cores": head["threads"],
+        "kind": "oracle",
+        "sample": f"x, y and z passes of one 512^3 heat step (D_0, order 6, Dirichlet) over {lines} lines of "
+                  f"512 points each ({sample_dof_apps} DOF applications per run), {warm} warm-ups + {reps} runs, "
+                  "median; reference build -O2 -ffp-contract=off",
+        "timings": timings,
+        "builds": {"reference": " ".join(oracle.REFERENCE_FLAGS), "native": " ".join(oracle.NATIVE_FLAGS)},
+        "host": host_info(),
+        "gpu_max_err_vs_oracle_rel_to_max_v": err,
+        "context": "paper: > 1e8 DOF/node/s per whole 2-D time step on 40 Xeon Gold 6148 cores (CPU nodes)",
+    }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side 3-D heat legs")
+    ap.add_argument("--no-extra", action="store_true", help="headline only (no beside legs)")
+    ap.add_argument("--only", choices=("heat3d_f64", "heat3d_mixed", "advdiff2d", "line1d", "batch", "hj", "copy"))
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -346,64 +512,57 @@ def main():
     import torch
 
     import paper_2007_03041_amd as sc
-    from paper_2007_03041_amd import workloads as W
 
     if args.calibrate_copy:
-        calibrate_copy(torch)
+        # a plain copy of known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings
+        print(json.dumps(copy_leg(torch, reps=5)))
+        return
+    sc.load()
+    if args.only:
+        if args.only in ("heat3d_f64", "heat3d_mixed"):
+            rec = heat3d(sc, torch, args.only.split("_")[1], args.steps, args.warmup)[0]
+        elif args.only == "advdiff2d":
+            rec = advdiff2d(sc, torch, args.steps, args.warmup)
+        elif args.only == "line1d":
+            rec = line1d(sc, torch, args.steps, args.warmup)
+        elif args.only == "batch":
+            rec = batch_legs(sc, torch)
+        elif args.only == "hj":
+            rec = hj_legs(sc, torch)
+        else:
+            rec = copy_leg(torch)
+        print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 
-    sc.load()
-    L = 2 * math.pi
-    dx = L / N
-    grid = sc.Grid((N, N), (0.0, 0.0), (L, L))
-    pde_kw = dict(c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dx, order=ORDER, split=True)
-    pde = sc.make_pde(**pde_kw)
-    fields = [W.fourier_field(N, N, device="cuda") for _ in range(NFIELDS)]
-    stepper = sc.TimeStepper(grid, pde)
-
-    for i in range(args.warmup):
-        stepper.step(fields[i % NFIELDS], 1)
-    torch.cuda.synchronize()
-
-    it = iter(range(1 << 62))
-    t, name, mean_ms, kernel_ms = measure(sc, torch, lambda: stepper.step(fields[next(it) % NFIELDS], 1),
-                                          args.steps)
-
-    ms_per_step = 1e3 * t / args.steps
-    dof = N * N
-    value = dof * OPS_PER_STEP / (t / args.steps)
-
-    # dominant kernel: the one with the largest total time per step; its mean launch time is taken
-    # from the events around its launches in the measured region
-    avg_s = mean_ms / 1e3
-    # one fused or apply launch reads the operand and writes the result over every DOF once;
-    # an aggregate-only launch (chunked passes) reads it once and writes per-chunk scalars
-    alg_bytes = (8 if "agg" in name else BYTES_PER_DOF_PASS) * dof
-    achieved = alg_bytes / avg_s / 1e9
-    traffic = load_traffic(name)
-
+    head, m, u64 = heat3d(sc, torch, "f64", args.steps, args.warmup)
+    dof = HEAT_N ** 3
+    name = m["dominant"]
+    alg_bytes = 16 * dof
+    achieved = alg_bytes / (m["dominant_mean_ms"] / 1e3) / 1e9
     out = {
-        "metric": "DOF updates/s per L^{-1}/D application on 1 GPU; % HBM roofline; error vs FP64",
-        "value": value,
+        "metric": METRIC,
+        "value": head["dof_applications_per_s"],
         "unit": "DOF*applications/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "2-D linear advection-diffusion, 4096x4096 periodic on [0,2pi]^2, FP64, "
-                        "order-4 local quadrature, dimension-split x then y, dt=dx, beta=1, "
-                        "8 seeded Fourier modes",
-            "grid": [N, N],
-            "operator_applications_per_step": OPS_PER_STEP,
-            "fields_rotated": NFIELDS,
-            "paper_metric_dof_per_s": dof / (t / args.steps),
-            "kernel_ms": kernel_ms,
+            "workload": "3-D heat equation, 512^3 incl. boundaries on [0,1]^3, Dirichlet 0, FP64, order-6 local "
+                        "quadrature, dimension-split x, y, z passes of u <- u - D_0 u, dt=dx, beta=1, "
+                        "16 seeded Gaussian bumps",
+            "grid": [HEAT_N] * 3,
+            "operator_applications_per_step": 3,
+            "paper_metric_dof_per_s": head["paper_metric_dof_per_s"],
+            "step_ms_min": head["step_ms_min"],
+            "step_ms_median": head["step_ms_median"],
+            "kernel_ms": head["kernel_ms"],
+            "kernel_source_sha": kernel_source_sha(),
         },
         "roofline": {
             "bound": "hbm",
@@ -412,20 +571,47 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": load_traffic("heat3d_f64", name),
             "algorithmic_bytes_per_launch": alg_bytes,
-            "mean_launch_ms": avg_s * 1e3,
+            "mean_launch_ms": m["dominant_mean_ms"],
+            "per_pass": head["per_pass"],
+            "step": head["step"],
         },
     }
     if not args.no_extra:
-        del fields, stepper
-        out["beside"] = {"heat3d_512": heat3d_legs(sc, torch)}
+        del u64
         torch.cuda.empty_cache()
-        out["beside"]["batch_4096"] = batch_legs(sc, torch)
+        beside = {}
+        mixed, _, u32 = heat3d(sc, torch, "mixed", args.steps, args.warmup)
+        del u32
+        # the two paths on the same initial data and number of steps: the mixed path's error
+        from paper_2007_03041_amd import workloads as W
+
+        g64 = sc.Grid((HEAT_N,) * 3, (0.0,) * 3, (1.0,) * 3, ("dirichlet",) * 3)
+        import dataclasses
+
+        g32 = dataclasses.replace(g64, dtype=sc.SC_F32_MIXED)
+        pde = sc.make_pde(nu_diff=1.0, beta=1.0, dt=1.0 / (HEAT_N - 1), order=6, split=True)
+        a = W.bump_field(HEAT_N, device="cuda")
+        b = a.to(torch.float32)
+        sc.TimeStepper(g64, pde).step(a, 5)
+        sc.TimeStepper(g32, pde).step(b, 5)
+        mixed["max_rel_err_vs_f64_path_5_steps"] = ((b.double() - a).abs().max() / a.abs().max()).item()
+        del a, b
         torch.cuda.empty_cache()
-        out["beside"]["hamilton_jacobi_2048"] = hj_legs(sc, torch)
+        beside["heat3d_512_mixed"] = mixed
+        beside["advdiff2d_4096"] = advdiff2d(sc, torch, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        beside["line1d_replicated"] = line1d(sc, torch, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        beside["device_copy_1GiB"] = copy_leg(torch)
+        torch.cuda.empty_cache()
+        beside["batch_4096"] = batch_legs(sc, torch)
+        torch.cuda.empty_cache()
+        beside["hamilton_jacobi_2048"] = hj_legs(sc, torch)
+        out["beside"] = beside
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, torch, grid, pde_kw)
+        out["cpu_baseline"] = cpu_baseline(sc, torch)
     print(json.dumps(out), flush=True)
 
 

@@ -262,7 +262,7 @@ sc_status sc_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  * Reading synchronises the events. */
 sc_status sc_timing_enable(int on);
 /* Restrict the timing to the launches whose kernel names appear in `names` (comma-separated, e.g.
- * "line_pass_apply_yz,line_pass_fused_x"); NULL or "" times every launch.  Each timed launch adds
+ * "line_pass_apply_y,line_pass_fused_x"); NULL or "" times every launch.  Each timed launch adds
  * two event records to the stream, so a benchmark that times one kernel inside its measured region
  * selects just that kernel.  The string is copied; SC_ERR_ARG if it is longer than 1023 bytes. */
 sc_status sc_timing_select(const char *names);

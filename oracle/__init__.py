@@ -31,12 +31,24 @@ _OPS = {"L": OP_L, "R": OP_R, "0": OP_0, 0: OP_L, 1: OP_R, 2: OP_0}
 _BCS = {"periodic": BC_PERIODIC, "dirichlet": BC_DIRICHLET, 0: BC_PERIODIC, 1: BC_DIRICHLET}
 
 
+NATIVE_LIB_PATH = os.path.join(_HERE, "liboracle_native.so")
+REFERENCE_FLAGS = ["-O2", "-ffp-contract=off"]
+NATIVE_FLAGS = ["-O3", "-march=native"]
+
+
 def build() -> str:
     """Compile the oracle with gcc (plain C, OpenMP over independent lines)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH,
-           _SRC, "-lm"]
+    cmd = ["gcc", *REFERENCE_FLAGS, "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH, _SRC, "-lm"]
     subprocess.check_call(cmd, cwd=_HERE)
     return LIB_PATH
+
+
+def build_native() -> str:
+    """A second build of the same source with ``-O3 -march=native`` (contraction allowed), for CPU
+    timing only: every test checks results of the reference build."""
+    cmd = ["gcc", *NATIVE_FLAGS, "-fopenmp", "-shared", "-fPIC", "-o", NATIVE_LIB_PATH, _SRC, "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    return NATIVE_LIB_PATH
 
 
 class _Grid(ctypes.Structure):
@@ -50,14 +62,32 @@ class _Pde(ctypes.Structure):
 
 
 _lib = None
+_libs = {}
+_build_kind = "reference"
+
+
+def use_build(kind: str) -> None:
+    """Route every call of this module to the ``reference`` build (``-O2 -ffp-contract=off``, the
+    default) or the ``native`` timing build (``-O3 -march=native``)."""
+    global _lib, _build_kind
+    if kind not in ("reference", "native"):
+        raise ValueError("build kind: reference or native")
+    _build_kind = kind
+    _lib = _libs.get(kind)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the loops over lines in the current build; returns the count now in effect."""
+    return int(_load().sco_set_threads(int(n)))
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(LIB_PATH)
+        path = LIB_PATH if _build_kind == "reference" else NATIVE_LIB_PATH
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build() if _build_kind == "reference" else build_native()
+        lib = ctypes.CDLL(path)
         dp = POINTER(c_double)
         lib.sco_weights.argtypes = [c_double, c_int, POINTER(c_int), dp]
         lib.sco_line_quad.argtypes = [c_int, c_int, c_double, c_double, c_int64, dp, dp, dp]
@@ -72,10 +102,12 @@ def _load():
                                                 c_double, dp, dp, dp]
         lib.sco_time_step.argtypes = [gp, POINTER(_Pde), c_int, dp]
         lib.sco_num_threads.argtypes = []
+        lib.sco_set_threads.argtypes = [c_int]
         for f in ("sco_weights", "sco_line_quad", "sco_line_sweep", "sco_line_invL",
                   "sco_local_quad", "sco_sweep_LR", "sco_apply_invL",
-                  "sco_apply_D_partial_sum", "sco_time_step", "sco_num_threads"):
+                  "sco_apply_D_partial_sum", "sco_time_step", "sco_num_threads", "sco_set_threads"):
             getattr(lib, f).restype = c_int
+        _libs[_build_kind] = lib
         _lib = lib
     return _lib
 

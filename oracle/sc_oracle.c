@@ -393,3 +393,15 @@ int sco_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops over lines (for timing single-thread and all-core runs). */
+int sco_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -253,10 +253,13 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
         return fail(SC_ERR_UNSUPPORTED, "internal: fused powers of D need one periodic operator on whole lines");
     const int64_t tiles = (ax.nlines + scx::variant(vid).TC - 1) / scx::variant(vid).TC;
     if (tiles * a.nchunks > (int64_t)INT32_MAX) return fail(SC_ERR_SHAPE, "too many lines for one launch");
-    const bool contig = scx::variant(vid).contig;
+    // timing names carry the axis: its stride decides the memory access pattern
+    static const char *const kFused[3] = {"line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z"};
+    static const char *const kAgg[3] = {"line_pass_agg_x", "line_pass_agg_y", "line_pass_agg_z"};
+    static const char *const kApply[3] = {"line_pass_apply_x", "line_pass_apply_y", "line_pass_apply_z"};
     hipError_t e;
     if (a.nchunks == 1) {
-        e = timed(contig ? "line_pass_fused_x" : "line_pass_fused_yz", st, [&](const char **) {
+        e = timed(kFused[dim], st, [&](const char **) {
             return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -270,13 +273,13 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     // lines of few chunks: every apply tile forms its own carries from the chunk totals (one launch
     // less); longer lines go through the carry launch
     a.fuse_carry = a.nchunks <= kFuseCarryChunks ? 1 : 0;
-    e = timed(contig ? "line_pass_agg_x" : "line_pass_agg_yz", st, [&](const char **) {
+    e = timed(kAgg[dim], st, [&](const char **) {
         return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_AGG, false, st);
     });
     if (e == hipSuccess && !a.fuse_carry)
         e = timed("chunk_carry", st, [&](const char **) { return scx::launch_chunk_carry(a, st); });
     if (e == hipSuccess)
-        e = timed(contig ? "line_pass_apply_x" : "line_pass_apply_yz", st, [&](const char **) {
+        e = timed(kApply[dim], st, [&](const char **) {
             return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_APPLY, false, st);
         });
     if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -560,15 +563,33 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
         }
         return SC_OK;
     }
+    // Dimension-split steps alternate between u and the workspace pass by pass; after an odd number
+    // of passes the result would sit in the workspace and need a copy back (a full-field read and
+    // write).  A pass whose lines fit one tile reads all of its operand into the tile before it
+    // writes, so it can run in place: the last such pass of the call does, and the result ends in u.
+    int64_t inplace_pass = -1;
+    if (pde->split) {
+        int per_step = 0, last_fused = -1;
+        for (int d = 0; d < grid->ndim; ++d)
+            if (nops[d]) {
+                if (nchunks_for(axis_of(grid, d), (int)elem_bytes(grid)) == 1) last_fused = per_step;
+                ++per_step;
+            }
+        const int64_t passes = (int64_t)per_step * nsteps;
+        if ((passes & 1) && last_fused >= 0) inplace_pass = passes - per_step + last_fused;
+    }
+    int64_t pass = 0;
     for (int step = 0; step < nsteps; ++step) {
         bool first = true;
         for (int d = 0; d < grid->ndim; ++d) {
             if (!nops[d]) continue;
             if (pde->split) {
                 // one 1-D step on the current state: nxt = cur + sum_ops scale * D[cur]
-                s = run_pass(grid, d, pde->order, ops[d], nops[d], cur, nullptr, 1, nxt, nullptr, rest, rest_bytes, st);
+                const bool inplace = pass++ == inplace_pass;
+                s = run_pass(grid, d, pde->order, ops[d], nops[d], cur, nullptr, 1, inplace ? cur : nxt, nullptr, rest,
+                             rest_bytes, st);
                 if (s != SC_OK) return s;
-                std::swap(cur, nxt);
+                if (!inplace) std::swap(cur, nxt);
                 continue;
             }
             // unsplit: every axis reads u^n (cur); nxt accumulates u^n + all D terms

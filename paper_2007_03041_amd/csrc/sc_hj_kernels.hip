@@ -13,6 +13,8 @@
 //                    adaptive rule: the reduction of one step feeds the next)
 //   mlp_forward / mlp_train_tile / mlp_reduce_grads / mlp_adam: inference and training of the proposer
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <stdint.h>
 
 #include "sc_hj_dev.h"
@@ -760,19 +762,22 @@ __global__ void __launch_bounds__(256) mlp_reduce_grads(const float *__restrict_
 }
 
 // Adam (Kingma & Ba) on the FP32 master parameters; t = step number (>= 1).
+// Adam (Kingma & Ba) in FP32.  The constants b1, 1 - b1, b2, 1 - b2 and the bias corrections
+// 1 / (1 - b^t) are formed in FP64 on the host and rounded once: 1 - fl32(0.999) alone is 1.3e-5
+// away from 0.001.
 __global__ void __launch_bounds__(256) mlp_adam(float *__restrict__ P, const float *__restrict__ grad,
-                                                float *__restrict__ M, float *__restrict__ V, int t, float lr,
-                                                float b1, float b2, float eps)
+                                                float *__restrict__ M, float *__restrict__ V, float lr, float b1,
+                                                float omb1, float b2, float omb2, float c1, float c2, float eps)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= MLP_NPARAM) return;
     const float gk = grad[k];
-    const float mk = b1 * M[k] + (1.f - b1) * gk;
-    const float vk = b2 * V[k] + (1.f - b2) * gk * gk;
+    const float mk = b1 * M[k] + omb1 * gk;
+    const float vk = b2 * V[k] + omb2 * gk * gk;
     M[k] = mk;
     V[k] = vk;
-    const float mh = mk / (1.f - powf(b1, (float)t));
-    const float vh = vk / (1.f - powf(b2, (float)t));
+    const float mh = mk * c1;
+    const float vh = vk * c2;
     P[k] = P[k] - lr * mh / (sqrtf(vh) + eps);
 }
 
@@ -854,8 +859,11 @@ hipError_t launch_mlp_grad(const float *P, const float *X, const float *Y, int64
 
 hipError_t launch_mlp_adam(float *P, const float *grad, float *M, float *V, int t, float lr, hipStream_t st)
 {
-    hipLaunchKernelGGL(mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, P, grad, M, V, t, lr, 0.9f, 0.999f,
-                       1e-8f);
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)t)));
+    hipLaunchKernelGGL(mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, P, grad, M, V, lr, (float)b1,
+                       (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), c1, c2, 1e-8f);
     return hipGetLastError();
 }
 

@@ -585,8 +585,12 @@ __device__ __forceinline__ int64_t xcd_grouped(int64_t b, int64_t nblocks)
     return b < whole ? (b % NX) * (whole / NX) + b / NX : b;
 }
 
+// Single-power passes are held to 128 VGPRs (4 waves per SIMD): left alone, the compiler gave the
+// one-operator x passes 129-131 and so one workgroup per CU less.  The fused powers of D keep their
+// registers (about 210): they would spill.
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI, bool FULL>
-__global__ void __launch_bounds__(NT) line_pass(const PassArgs a)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MULTI ? 1 : 4)))
+line_pass(const PassArgs a)
 {
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
     const int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;

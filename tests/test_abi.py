@@ -108,12 +108,12 @@ def test_timing_select_parses_and_validates():
     selection, lists over 1023 bytes are rejected; nothing touches the device and no launch is timed
     while timing is off."""
     lib = sc.load()
-    assert lib.sc_timing_select(b"line_pass_fused_x,,line_pass_apply_yz,") == sc.SC_OK
+    assert lib.sc_timing_select(b"line_pass_fused_x,,line_pass_apply_y,") == sc.SC_OK
     assert lib.sc_timing_select(None) == sc.SC_OK
     assert lib.sc_timing_select(b"") == sc.SC_OK
     assert lib.sc_timing_select(b"x" * 1024) == sc.SC_ERR_ARG
     assert "1023" in lib.sc_last_error().decode()
-    sc.timing_select(["line_pass_agg_yz"])
+    sc.timing_select(["line_pass_agg_y"])
     sc.timing_select(None)
     assert sc.timing_read() == {}
 

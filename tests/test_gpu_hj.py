@@ -118,6 +118,7 @@ def test_mlp_gradients_match_oracle(gpu_lib):
         d = np.abs(gg[k] - g[k])
         assert (d <= bound).all(), (k, float((d / bound).max()))
         frac_tight.append(float((d <= 1e-3 * mag + 1e-12).mean()))
+        print(f"gradients {k}: max |diff| / magnitude {float((d / (mag + 1e-30)).max()):.2e}")
     print("gradients: fraction of elements within 1e-3 of their magnitude:", frac_tight)
     assert min(frac_tight) > 0.9
 

@@ -264,6 +264,21 @@ def test_time_step_3d_dirichlet_heat_split(gpu_lib):
     assert err(host(u), ref, np.abs(ref).max()) < TOL
 
 
+@pytest.mark.parametrize("nsteps", [1, 2, 3])
+def test_time_step_split_in_place_pass(gpu_lib, nsteps):
+    """Dimension-split steps with an odd number of passes run the last pass whose lines fit one tile
+    in place; here z lines are chunked (9000 points), so that pass is the y pass of the last step."""
+    sc = gpu_lib
+    n = (24, 20, 9000)
+    u0 = W.random_field((n[2], n[1], n[0]), index=93)
+    g = Grid(n, (0, 0, 0), (1.0, 1.0, 30.0))
+    dt = 1.0 / 24
+    ref = oracle.time_step(ogrid(g), (0.5, -1.0, 2.0), 0.2, 1.0, dt, 6, nsteps, u0, split=True)
+    u = dev(u0)
+    sc.time_step(u, g, nsteps, c=(0.5, -1.0, 2.0), nu_diff=0.2, beta=1.0, dt=dt, order=6, split=True)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
+
+
 def test_time_step_3d_dirichlet_heat(gpu_lib):
     sc = gpu_lib
     n = 33
@@ -303,6 +318,24 @@ def test_config2_full_size_one_step_sampled(gpu_lib):
             e0 = col - oracle.line_invL("periodic", "0", 4, a_dif, dx, col)
             ref = u0[j, i] - dR[i] - d0[i] - eR[j] - e0[j]
             assert abs(got[j, i] - ref) < TOL * np.abs(u0).max()
+
+
+def test_config2_full_field_split_steps(gpu_lib):
+    """4096^2, order 4, two dimension-split steps exactly as the benchmark runs them (sc_time_step,
+    split, one call per step): every element against the oracle's two split steps."""
+    sc = gpu_lib
+    N = 4096
+    L = 2 * np.pi
+    dx = L / N
+    g = Grid((N, N), (0, 0), (L, L))
+    u0 = W.fourier_field(N, N)
+    ref = oracle.time_step(ogrid(g), (1.0, 1.0), 1.0, 1.0, dx, 4, 2, u0, split=True)
+    u = dev(u0)
+    pde = sc.make_pde(c=(1.0, 1.0), nu_diff=1.0, beta=1.0, dt=dx, order=4, split=True)
+    st = sc.TimeStepper(g, pde)
+    st.step(u, 1)
+    st.step(u, 1)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
 
 
 def test_config2_ten_steps_match_mode_symbols(gpu_lib):
@@ -415,7 +448,7 @@ def test_timing_select_times_only_the_named_kernels(gpu_lib):
     u = dev(W.random_field((64, 2048), index=5))
     try:
         sc.timing_reset()
-        sc.timing_select(["line_pass_fused_yz"])
+        sc.timing_select(["line_pass_fused_y"])
         sc.timing_enable(True)
         sc.time_step(u, g, 2, c=(1.0, 1.0), nu_diff=0.5, beta=1.0, dt=1.0 / 2048, order=4, split=True)
         torch.cuda.synchronize()
@@ -432,6 +465,6 @@ def test_timing_select_times_only_the_named_kernels(gpu_lib):
         sc.timing_enable(False)
         sc.timing_reset()
         sc.timing_select(None)
-    assert set(sel) == {"line_pass_fused_yz"} and sel["line_pass_fused_yz"][1] == 2
-    assert {"line_pass_fused_x", "line_pass_fused_yz"} <= set(every)
+    assert set(sel) == {"line_pass_fused_y"} and sel["line_pass_fused_y"][1] == 2
+    assert {"line_pass_fused_x", "line_pass_fused_y"} <= set(every)
     assert all(cnt == 2 and ms > 0 for ms, cnt in every.values())
