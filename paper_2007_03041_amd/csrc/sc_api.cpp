@@ -119,6 +119,12 @@ int pick_variant(bool contig, int64_t n, int elem)
     return 6;  // 16 lines x 1024
 }
 
+bool pipe_enabled()
+{
+    const char *env = std::getenv("SC_PIPE");
+    return !(env && env[0] == '0');
+}
+
 // decay from the start of the last real wave-part of a tile to the tile's last real point
 double last_part_decay(double nu, int64_t n_loc, const scx::Variant &V)
 {
@@ -259,8 +265,14 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     static const char *const kApply[3] = {"line_pass_apply_x", "line_pass_apply_y", "line_pass_apply_z"};
     hipError_t e;
     if (a.nchunks == 1) {
+        // strided lines of exactly one tile whose tiles are adjacent, aligned lines: the pipelined
+        // persistent form (SC_PIPE=0 turns it off, for comparisons)
+        const scx::Variant &V = scx::variant(vid);
+        const bool pipe = !V.contig && !multi && scx::pipe_variant(vid, elem) && ax.n == V.C() && ax.nlines % V.TC == 0 &&
+                          ax.stride % V.TC == 0 && ((uintptr_t)v & 15) == 0 && pipe_enabled();
         e = timed(kFused[dim], st, [&](const char **) {
-            return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
+            return pipe ? scx::launch_line_pass_pipe(a, elem, order, vid, st)
+                        : scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         return SC_OK;

@@ -13,6 +13,10 @@ extern template hipError_t launch_line_pass_t<float, 4, false>(const PassArgs &,
 extern template hipError_t launch_line_pass_t<float, 4, true>(const PassArgs &, int, int, bool, hipStream_t);
 extern template hipError_t launch_line_pass_t<float, 6, false>(const PassArgs &, int, int, bool, hipStream_t);
 extern template hipError_t launch_line_pass_t<float, 6, true>(const PassArgs &, int, int, bool, hipStream_t);
+extern template hipError_t launch_line_pass_pipe_t<double, 4>(const PassArgs &, int, hipStream_t);
+extern template hipError_t launch_line_pass_pipe_t<double, 6>(const PassArgs &, int, hipStream_t);
+extern template hipError_t launch_line_pass_pipe_t<float, 4>(const PassArgs &, int, hipStream_t);
+extern template hipError_t launch_line_pass_pipe_t<float, 6>(const PassArgs &, int, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<double, 4>(const BatchLaunch &, int, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<double, 6>(const BatchLaunch &, int, hipStream_t);
 extern template hipError_t launch_line_pass_batch_t<float, 4>(const BatchLaunch &, int, hipStream_t);
@@ -213,6 +217,20 @@ hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int
                     : launch_line_pass_t<float, 4, false>(a, vid, mode, multi, st);
     return full ? launch_line_pass_t<float, 6, true>(a, vid, mode, multi, st)
                 : launch_line_pass_t<float, 6, false>(a, vid, mode, multi, st);
+}
+
+bool pipe_variant(int vid, int elem) { return (vid == 5 && elem == 8) || vid == 12; }
+
+hipError_t launch_line_pass_pipe(const PassArgs &a, int elem, int order, int vid, hipStream_t st)
+{
+    if (!pipe_variant(vid, elem) || !variant_built(vid, elem)) return hipErrorInvalidValue;
+    const Variant &V = variant(vid);
+    // the shape the pipelined loads assume (checked again here, whatever the caller checked)
+    if (V.contig || a.n != V.C() || a.nlines % V.TC || a.stride % V.TC || ((uintptr_t)a.v & 15) || a.nops < 1 ||
+        a.nops > 2)
+        return hipErrorInvalidValue;
+    if (elem == 8) return order == 4 ? launch_line_pass_pipe_t<double, 4>(a, vid, st) : launch_line_pass_pipe_t<double, 6>(a, vid, st);
+    return order == 4 ? launch_line_pass_pipe_t<float, 4>(a, vid, st) : launch_line_pass_pipe_t<float, 6>(a, vid, st);
 }
 
 hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st)

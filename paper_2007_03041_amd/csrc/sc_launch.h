@@ -17,6 +17,10 @@ bool variant_built(int vid, int elem);
 // elem = 8 (FP64) or 4 (FP32 data, mixed-precision carries)
 hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int mode, bool multi, hipStream_t st);
 hipError_t launch_chunk_carry(const PassArgs &a, hipStream_t st);
+// Pipelined strided pass (variants 5 and 12; lines of exactly C points, line count and stride
+// multiples of TC, operand 16-byte aligned): see line_pass_pipe.
+hipError_t launch_line_pass_pipe(const PassArgs &a, int elem, int order, int vid, hipStream_t st);
+bool pipe_variant(int vid, int elem);
 hipError_t launch_local_quad(const PassArgs &a, int elem, int order, void *JL, void *JR, hipStream_t st);
 hipError_t launch_sweep(const PassArgs &a, int elem, const void *JL, const void *JR, void *IL, void *IR,
                         double *ends, hipStream_t st);
@@ -46,6 +50,8 @@ hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items
 // one instantiation unit per (element type, order, full tiles or not): sc_lp_<type>_o<order>[_full].hip
 template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st);
+template <typename T, int ORDER>
+hipError_t launch_line_pass_pipe_t(const PassArgs &a, int vid, hipStream_t st);
 template <typename T, int ORDER>
 hipError_t launch_line_pass_batch_t(const BatchLaunch &b, int vid, hipStream_t st);
 template <typename T, int ORDER>

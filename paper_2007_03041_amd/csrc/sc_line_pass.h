@@ -45,6 +45,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sc_device.h"
 #include "sc_launch.h"
 
@@ -377,6 +379,35 @@ __device__ __forceinline__ void chunk_scan_regs(const OA &P, const double (&tf)[
     IL0 = F;
 }
 
+// A wave-uniform 64-bit value the compiler cannot see through (the asm exists in the device pass
+// only; the host pass never runs kernel bodies).
+__device__ __forceinline__ uint64_t launder_sgpr(uint64_t x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(x));
+#endif
+    return x;
+}
+
+// Direct global-to-LDS load of 16 bytes a lane: lane l's bytes land at lds_dst + 16 l (lds_dst
+// wave-uniform).  (The builtin exists in the device pass only.)
+template <typename T>
+__device__ __forceinline__ void load_lds16(const T *src, T *lds_dst)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0, 0);
+#endif
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
+// outstanding global loads -- a direct-to-LDS prefetch of the next tile keeps streaming across it
+// (a __syncthreads fence would wait for it).  The memory clobber keeps the compiler from moving
+// memory accesses across.
+__device__ __forceinline__ void barrier_lds()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Operand loads are ordinary cached loads: a window's halo rows are read again by the neighbouring
 // segment's thread, and a streaming (non-temporal) hint evicted them before that second read (the
 // aggregate launch then fetched 14 % more than the field and ran 25 % longer).
@@ -592,10 +623,46 @@ template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, i
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MULTI ? 1 : 4)))
 line_pass(const PassArgs a)
 {
+    constexpr bool PIPE = false;
+    constexpr bool pipe_first = false;
+    constexpr int64_t pipe_next = -1;
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
     const int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int tid_in = threadIdx.x;
 #include "sc_line_pass_body.inc"
+}
+
+// Persistent strided pass over whole lines (y/z lines that fit one tile): workgroup b takes line
+// tiles b, b + grid, ...  Each tile's operand goes straight from memory to LDS; the loads of the
+// next tile are issued as soon as the windows of the current one are in registers, so they stream
+// in during the current tile's scans, re-sweeps and stores.
+template <typename T, int ORDER, int S, int TC, int NT, int NOPS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+line_pass_pipe(const PassArgs a_arg, int64_t ntiles)
+{
+    constexpr bool CONTIG = false;
+    constexpr int MODE = MODE_FUSED;
+    constexpr bool MULTI = false;
+    constexpr bool FULL = true;
+    constexpr bool PIPE = true;
+    (void)a_arg;
+    // The argument block is read through the kernel-argument segment (the explicit arguments start
+    // at its offset 0), with the pointer laundered per tile: otherwise the loop-invariant coefficient
+    // reads are hoisted out of the loop and their scalar registers spill.
+    typedef const PassArgs __attribute__((address_space(4))) CPassArgs;
+    for (int64_t blk = blockIdx.x; blk < ntiles; blk += gridDim.x) {
+        const bool pipe_first = blk == (int64_t)blockIdx.x;
+        const int64_t pipe_next = blk + gridDim.x < ntiles ? blk + gridDim.x : -1;
+        const auto &a = *(const CPassArgs *)launder_sgpr((uint64_t)__builtin_amdgcn_kernarg_segment_ptr());
+        const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
+        // the thread index is laundered per tile, as in the batched kernel
+        int tid_in = threadIdx.x;
+        asm volatile("" : "+v"(tid_in));
+        {
+#include "sc_line_pass_body.inc"
+        }
+        barrier_lds();  // the next tile reuses the LDS tables (its loads are waited for at its start)
+    }
 }
 
 // Persistent pass over a batch of independent instances: workgroup b takes work items b, b + grid,
@@ -610,6 +677,9 @@ line_pass_batch(const BatchArgs *__restrict__ table,
     constexpr int NOPS = 1;
     constexpr bool MULTI = false;
     constexpr bool FULL = false;
+    constexpr bool PIPE = false;
+    constexpr bool pipe_first = false;
+    constexpr int64_t pipe_next = -1;
     // the table and work list are read-only for the whole launch: reading them through the constant
     // address space makes every per-instance parameter a scalar load, as for kernel arguments
     typedef const BatchArgs __attribute__((address_space(4))) CBatchArgs;
@@ -685,6 +755,53 @@ hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, 
     return hipErrorInvalidValue;
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Pipelined strided passes (whole lines of C points, FULL tiles)
+// ------------------------------------------------------------------------------------------
+// static LDS of a pipelined tile: [point][line] tile without padding plus the tables of Variant
+template <typename T, int ORDER, int S, int TC, int NT, int NOPS>
+constexpr int pipe_lds_bytes()
+{
+    constexpr Variant V{S, TC, false, NT};
+    return V.lds_bytes((int)sizeof(T), ORDER, NOPS) - TC * ((((V.C() + ORDER + 31) & ~31) + 1)) * (int)sizeof(T) +
+           (V.C() + ORDER) * TC * (int)sizeof(T) + 64;
+}
+
+template <typename T, int ORDER, int S, int TC, int NT, int NOPS>
+static hipError_t launch_pipe_shape(const PassArgs &a, hipStream_t st)
+{
+    if constexpr (pipe_lds_bytes<T, ORDER, S, TC, NT, NOPS>() > LDS_LIMIT) {
+        return hipErrorInvalidValue;
+    } else {
+    const int64_t ntiles = a.nlines / TC;
+    // resident workgroups of the whole device (one grid's worth), found once per process
+    static const int64_t resident = [] {
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, reinterpret_cast<const void *>(&line_pass_pipe<T, ORDER, S, TC, NT, NOPS>), NT, 0) != hipSuccess)
+            return int64_t(0);
+        return (int64_t)(occ > 0 ? occ : 1) * cus;
+    }();
+    if (resident <= 0) return hipErrorInvalidValue;
+    const int64_t grid = std::min<int64_t>(ntiles, resident);
+    hipLaunchKernelGGL((line_pass_pipe<T, ORDER, S, TC, NT, NOPS>), dim3((unsigned)grid), dim3(NT), 0, st, a, ntiles);
+    return hipGetLastError();
+    }
+}
+
+template <typename T, int ORDER>
+hipError_t launch_line_pass_pipe_t(const PassArgs &a, int vid, hipStream_t st)
+{
+    constexpr bool F64 = sizeof(T) == 8;
+    if (vid == 5 && F64) return a.nops == 2 ? launch_pipe_shape<T, ORDER, 16, 16, 512, 2>(a, st)
+                                            : launch_pipe_shape<T, ORDER, 16, 16, 512, 1>(a, st);
+    if (vid == 12) return a.nops == 2 ? launch_pipe_shape<T, ORDER, 16, 32, 1024, 2>(a, st)
+                                      : launch_pipe_shape<T, ORDER, 16, 32, 1024, 1>(a, st);
+    return hipErrorInvalidValue;
+}
 
 // ------------------------------------------------------------------------------------------
 // Batched launches (contiguous variants only)

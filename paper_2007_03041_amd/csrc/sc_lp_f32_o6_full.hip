@@ -4,4 +4,5 @@
 
 namespace scx {
 template hipError_t launch_line_pass_t<float, 6, true>(const PassArgs &, int, int, bool, hipStream_t);
+template hipError_t launch_line_pass_pipe_t<float, 6>(const PassArgs &, int, hipStream_t);
 }  // namespace scx

@@ -4,4 +4,5 @@
 
 namespace scx {
 template hipError_t launch_line_pass_t<double, 4, true>(const PassArgs &, int, int, bool, hipStream_t);
+template hipError_t launch_line_pass_pipe_t<double, 4>(const PassArgs &, int, hipStream_t);
 }  // namespace scx

@@ -195,3 +195,19 @@ def test_repeat_runs_bitwise_identical_mixed(gpu_lib):
     a = host(sc.apply_invL(v, g, 1, "R", 4, 30.0)).copy()
     b = host(sc.apply_invL(v, g, 1, "R", 4, 30.0))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,dim,bc", [((64, 512, 160), 1, "dirichlet"), ((64, 160, 512), 2, "periodic")])
+def test_pipelined_strided_passes_mixed(gpu_lib, n, dim, bc):
+    """FP32 y/z lines of one 512-point tile: the persistent pipelined form (32 lines a tile, loaded
+    straight into LDS), more line tiles than resident workgroups."""
+    sc = gpu_lib
+    v = W.random_field((n[2], n[1], n[0]), index=150 + dim)
+    g = Grid(n, (0.0, 0.0, 0.0), (1.0, 2.0, 3.0), (bc, bc, bc))
+    alpha = 0.05 / g.dx(dim)
+    lines = v.size // n[dim]
+    gv = np.random.default_rng(8).uniform(-1, 1, (lines, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_invL(ogrid(g), dim, op, 6, alpha, v, gv)
+        got = host(sc.apply_invL(dev32(v), mixed(g), dim, op, 6, alpha, g=None if gv is None else dev64(gv)))
+        assert err(got, ref, np.abs(ref).max()) < TOL, op

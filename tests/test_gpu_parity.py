@@ -468,3 +468,60 @@ def test_timing_select_times_only_the_named_kernels(gpu_lib):
     assert set(sel) == {"line_pass_fused_y"} and sel["line_pass_fused_y"][1] == 2
     assert {"line_pass_fused_x", "line_pass_fused_y"} <= set(every)
     assert all(cnt == 2 and ms > 0 for ms, cnt in every.values())
+
+
+# ------------------------------------------------------------------------------ pipelined strided passes
+PIPE_CASES = [
+    # (grid n (x, y, z), dim, bc, order): y and z lines of exactly one 512-point tile, enough line
+    # tiles that workgroups of the persistent launch take several
+    ((64, 512, 160), 1, "periodic", 6),
+    ((64, 160, 512), 2, "dirichlet", 4),
+    ((64, 512, 160), 1, "dirichlet", 6),
+    ((32, 96, 512), 2, "periodic", 4),
+]
+
+
+@pytest.mark.parametrize("n,dim,bc,order", PIPE_CASES)
+def test_pipelined_strided_whole_line_passes(gpu_lib, n, dim, bc, order):
+    """Strided passes whose lines fill one tile run persistent, their tiles loaded straight into LDS
+    while the previous tile is finished: every operator against the oracle, with Dirichlet values."""
+    sc = gpu_lib
+    v = W.random_field((n[2], n[1], n[0]), index=97 + dim)
+    g = Grid(n, (0.0, 0.0, 0.0), (1.0, 2.0, 3.0), (bc, bc, bc))
+    alpha = 0.07 / g.dx(dim)
+    lines = v.size // n[dim]
+    gv = np.random.default_rng(7).uniform(-1, 1, (lines, 2)) if bc == "dirichlet" else None
+    for op in OPS:
+        ref = oracle.apply_invL(ogrid(g), dim, op, order, alpha, v, gv)
+        got = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv)))
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+    ref = oracle.apply_D_partial_sum(ogrid(g), dim, "0", order, alpha, 1, -2.5, v, gv)
+    got = host(sc.apply_D_partial_sum(dev(v), g, dim, "0", order, alpha, 1, -2.5, g=None if gv is None else dev(gv)))
+    assert err(got, ref, 2.5 * np.abs(v).max()) < TOL
+
+
+def test_pipelined_passes_two_operators_in_a_time_step(gpu_lib):
+    """Advection and diffusion in one pass (two operators) on 512-point y and z lines, split steps
+    with the last pass in place."""
+    sc = gpu_lib
+    n = (48, 512, 512)
+    u0 = W.random_field((n[2], n[1], n[0]), index=99)
+    g = Grid(n, (0, 0, 0), (1.0, 4.0, 4.0))
+    dt = 1.0 / 48
+    ref = oracle.time_step(ogrid(g), (0.5, 1.0, -1.5), 0.1, 1.0, dt, 6, 1, u0, split=True)
+    u = dev(u0)
+    sc.time_step(u, g, 1, c=(0.5, 1.0, -1.5), nu_diff=0.1, beta=1.0, dt=dt, order=6, split=True)
+    assert err(host(u), ref, np.abs(ref).max()) < TOL
+
+
+def test_pipelined_and_tiled_passes_agree_bitwise(gpu_lib, monkeypatch):
+    """The pipelined form computes exactly what the tile-per-workgroup form computes (same
+    operations per point): SC_PIPE=0 selects the latter."""
+    sc = gpu_lib
+    n = (64, 512, 40)
+    v = dev(W.random_field((n[2], n[1], n[0]), index=98))
+    g = Grid(n, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ("dirichlet",) * 3)
+    a = host(sc.apply_invL(v, g, 1, "0", 6, 30.0)).copy()
+    monkeypatch.setenv("SC_PIPE", "0")
+    b = host(sc.apply_invL(v, g, 1, "0", 6, 30.0))
+    assert np.array_equal(a, b)
