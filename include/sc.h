@@ -61,7 +61,9 @@ typedef enum {
                         round their FP32 outputs once. */
 } sc_dtype;
 
-typedef enum { SC_OP_L = 0, SC_OP_R = 1, SC_OP_0 = 2 } sc_op; /* L_L^{-1}, L_R^{-1}, L_0^{-1} */
+/* L_L^{-1}, L_R^{-1}, L_0^{-1}.  Entry points take the operator as an int holding one of these
+ * values (any other value is rejected with SC_ERR_ARG). */
+typedef enum { SC_OP_L = 0, SC_OP_R = 1, SC_OP_0 = 2 } sc_op;
 typedef enum { SC_BC_PERIODIC = 0, SC_BC_DIRICHLET = 1 } sc_bc;
 
 typedef struct {
@@ -88,7 +90,7 @@ sc_status sc_sweep_LR(const sc_grid *grid, int dim, double alpha, const void *JL
 
 /* out = L_op^{-1}[v] along `dim` with the boundary constants of Sec. 2.3 (periodic) or the
  * Dirichlet values (2 per line, FP64, device; NULL = 0).  ws: see sc_workspace_bytes(). */
-sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+sc_status sc_apply_invL(const sc_grid *grid, int dim, int op, int order, double alpha,
                         const double *dirichlet_g, const void *v, void *out, void *ws,
                         size_t ws_bytes, sc_stream_t stream);
 
@@ -103,13 +105,13 @@ sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, doubl
  * one GPU (different streams, or threads) race and give wrong results; calls ordered on one stream
  * are safe, each writes every entry it reads. */
 #define SC_NOALLOC_SCRATCH_BYTES (8u << 20)
-sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, int op, int order, double alpha,
                                 const double *dirichlet_g, const void *v, void *out, sc_stream_t stream);
 
 /* out = scale * sum_{p=1..k} D^p[v], D = I - L_op^{-1} (Sec. 2.2, successive relation), k in 1..8.
  * scale = +alpha, -alpha, -alpha^2 gives the left-biased, right-biased and second derivative
  * representations.  Dirichlet axes support k = 1 only (SC_ERR_UNSUPPORTED otherwise). */
-sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order, double alpha,
                                  int k, double scale, const double *dirichlet_g, const void *v,
                                  void *out, void *ws, size_t ws_bytes, sc_stream_t stream);
 
@@ -208,7 +210,7 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
 
 /* ------------------------------------------------------------------------------------------------
- * Nonlinear Hamilton-Jacobi equation u_t + (u_x^2 + u_y^2) / 2 = 0 on a periodic 2-D grid (FP64,
+ * Nonlinear Hamilton-Jacobi equation u_t + H(u_x, u_y) = S on a periodic 2-D grid (FP64,
  * shape (n[1], n[0])), first order in time (Sec. 2.5): u <- u - dt H^ with the Lax-Friedrichs
  * numerical Hamiltonian H^ of the one-sided derivatives u_x^- = alpha D_R[u], u_x^+ = -alpha D_L[u]
  * (and likewise in y).  The local integrals use a 5-point WENO quadrature built from three 3-point
@@ -219,7 +221,10 @@ int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
  *                WENO-Z weights and replaced by them when some weight differs by more than theta.
  * Adaptive step with one lagged wave speed c (held on the device): dt = cfl min(dx, dy) / c, the
  * last step shortened to land on t_end; alpha = beta / (cfl min(dx, dy)) on both axes; the LF
- * dissipation is c; c is then replaced by the largest one-sided derivative of the step.
+ * dissipation is c; c is then replaced by the largest |H_p|, |H_q| over the step's one-sided
+ * derivatives.  This is the adaptive rule of Sec. 4.5 with its wave speeds taken equal (as the
+ * paper's own examples do); where max |H_p| = max |H_q| on a square grid -- Example 3, the data
+ * sin x + sin y -- it coincides with the per-axis rule dt = cfl min(dx / c_x, dy / c_y). 
  * state (device, 8 doubles): [c, t, steps, fallbacks, summed judged error, proposals judged, -, -].
  * ---------------------------------------------------------------------------------------------- */
 typedef struct {
@@ -228,7 +233,9 @@ typedef struct {
     double t_end;     /* steps stop advancing past t_end */
     double theta;     /* learned weights: largest accepted |proposal - WENO-Z| per weight */
     int32_t weights;  /* 0 linear, 1 WENO-Z, 2 learned */
-    int32_t reserved; /* 0 */
+    int32_t hamiltonian; /* 0: (u_x^2 + u_y^2) / 2; 1: Example 3 of Sec. 5.1, (1 + u_x + u_y)^2 / 2 with
+                            the source S = sin x + sin y + (1 + t cos x + t cos y)^2 / 2 of the
+                            manufactured solution u = t (sin x + sin y) on the right-hand side */
 } sc_hj_params;
 
 size_t sc_hj_workspace_bytes(const sc_grid *grid);

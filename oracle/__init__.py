@@ -85,7 +85,10 @@ def _load():
     global _lib
     if _lib is None:
         path = LIB_PATH if _build_kind == "reference" else NATIVE_LIB_PATH
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        override = os.environ.get("SC_ORACLE_LIBRARY_PATH")  # e.g. a sanitizer build (tests)
+        if override and _build_kind == "reference":
+            path = override
+        elif not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build() if _build_kind == "reference" else build_native()
         lib = ctypes.CDLL(path)
         dp = POINTER(c_double)

@@ -114,10 +114,78 @@ def derivatives(v: np.ndarray, alpha: float, dx: float, mode: str, omega=None):
     return alpha * (v - LR), -alpha * (v - LL)
 
 
-def hamiltonian_lf(pm, pp, qm, qp, rx, ry):
-    """Lax-Friedrichs numerical Hamiltonian of H(p, q) = (p^2 + q^2) / 2 (Sec. 2.5)."""
+def hamiltonian(p, q, kind: str = "quadratic"):
+    """H(p, q): 'quadratic' (p^2 + q^2) / 2 (the workload's equation) or 'ex3' (1 + p + q)^2 / 2
+    (Example 3 of Sec. 5.1)."""
+    if kind == "quadratic":
+        return 0.5 * (p * p + q * q)
+    s = 1.0 + p + q
+    return 0.5 * s * s
+
+
+def hamiltonian_lf(pm, pp, qm, qp, rx, ry, kind: str = "quadratic"):
+    """Lax-Friedrichs numerical Hamiltonian (Sec. 2.5): H at the averages of the one-sided
+    derivatives plus rx (p- - p+) / 2 + ry (q- - q+) / 2."""
     p, q = 0.5 * (pm + pp), 0.5 * (qm + qp)
-    return 0.5 * (p * p + q * q) + rx * 0.5 * (pm - pp) + ry * 0.5 * (qm - qp)
+    return hamiltonian(p, q, kind) + rx * 0.5 * (pm - pp) + ry * 0.5 * (qm - qp)
+
+
+def wave_speeds(pm, pp, qm, qp, kind: str = "quadratic"):
+    """(c_x, c_y) = (max |H_p|, max |H_q|) over the one-sided derivatives of a step."""
+    if kind == "quadratic":
+        return (float(max(np.abs(pm).max(), np.abs(pp).max())), float(max(np.abs(qm).max(), np.abs(qp).max())))
+    # H_p = H_q = 1 + p + q: its largest magnitude over the four one-sided combinations
+    m = max(float(np.abs(1.0 + a + b).max()) for a in (pm, pp) for b in (qm, qp))
+    return m, m
+
+
+def example3_source(x, y, t):
+    """Source of Example 3 (Sec. 5.1) for the manufactured solution u = t (sin x + sin y):
+    u_t + (1 + u_x + u_y)^2 / 2 = S with S = sin x + sin y + (1 + t cos x + t cos y)^2 / 2."""
+    return np.sin(x) + np.sin(y) + 0.5 * (1.0 + t * np.cos(x) + t * np.cos(y)) ** 2
+
+
+def hj_run_general(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1.0,
+                   kind: str = "quadratic", source=None, mode: str = "linear", max_steps: int = 100000):
+    """Forward-Euler steps of u_t + H(u_x, u_y) = S(x, y, t) on a periodic [0, L]^2 grid with the
+    adaptive rule of Sec. 4.5 with one wave speed per axis:
+      dt = CFL min(dx / c_x, dy / c_y),  alpha_x = beta / (c_x dt),  alpha_y = beta / (c_y dt)
+    (the alpha choice of Example 1 with the step's own dt and speeds, so the quadrature weights
+    change from step to step), Lax-Friedrichs coefficients c_x, c_y; the speeds of a step are the
+    largest |H_p|, |H_q| of the previous step's one-sided derivatives (lagged; initially of periodic
+    central differences of u0).  S is evaluated at the old time.  Returns (u, [(t, dt, c_x, c_y)])."""
+    u = np.array(u0, dtype=float)
+    ny, nx = u.shape
+    dx, dy = L / nx, L / ny
+    x = np.arange(nx) * dx
+    y = np.arange(ny) * dy
+    px = (np.roll(u, -1, axis=1) - np.roll(u, 1, axis=1)) / (2 * dx)
+    py = (np.roll(u, -1, axis=0) - np.roll(u, 1, axis=0)) / (2 * dy)
+    cx, cy = wave_speeds(px, px, py, py, kind)
+    t, hist = 0.0, []
+    for _ in range(max_steps):
+        if t >= T - 1e-14:
+            break
+        dt = min(cfl * min(dx / cx, dy / cy), T - t)
+        # alpha from the rule's full step (the last, shortened step keeps it)
+        dt_rule = cfl * min(dx / cx, dy / cy)
+        ax, ay = beta / (cx * dt_rule), beta / (cy * dt_rule)
+        pm = np.empty_like(u)
+        pp = np.empty_like(u)
+        qm = np.empty_like(u)
+        qp = np.empty_like(u)
+        for j in range(ny):
+            pm[j], pp[j] = derivatives(u[j], ax, dx, mode)
+        for i in range(nx):
+            qm[:, i], qp[:, i] = derivatives(u[:, i].copy(), ay, dy, mode)
+        rhs = hamiltonian_lf(pm, pp, qm, qp, cx, cy, kind)
+        if source is not None:
+            rhs = rhs - source(x[None, :], y[:, None], t)
+        u = u - dt * rhs
+        t += dt
+        cx, cy = wave_speeds(pm, pp, qm, qp, kind)
+        hist.append((t, dt, cx, cy))
+    return u, hist
 
 
 def hj_run(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1.0, mode: str = "linear",
@@ -159,20 +227,20 @@ def hj_run(u0: np.ndarray, L: float, T: float, cfl: float = 1.0, beta: float = 1
     return u, hist
 
 
-def hopf_lax_1d(x: np.ndarray, t: float, nquad: int = 20001) -> np.ndarray:
-    """Viscosity solution of w_t + w_x^2 / 2 = 0, w(x, 0) = sin x: w(x, t) = min_y sin y + (x - y)^2 / (2t),
-    minimised over a fine grid around every x and refined by golden-section search."""
+def hopf_lax_1d(x: np.ndarray, t: float, nquad: int = 20001, amp: float = 1.0) -> np.ndarray:
+    """Viscosity solution of w_t + w_x^2 / 2 = 0, w(x, 0) = amp sin x: w(x, t) = min_y amp sin y +
+    (x - y)^2 / (2t), minimised over a fine grid around every x and refined by golden-section search."""
     if t == 0.0:
-        return np.sin(x)
+        return amp * np.sin(x)
     out = np.empty_like(x)
     span = math.pi * 1.05 + t
     ys = np.linspace(-span, span, nquad)
     for k, xv in enumerate(x):
-        f = np.sin(xv + ys) + ys ** 2 / (2 * t)
+        f = amp * np.sin(xv + ys) + ys ** 2 / (2 * t)
         j = int(np.argmin(f))
         a, b = xv + ys[max(j - 1, 0)], xv + ys[min(j + 1, nquad - 1)]
         g = (math.sqrt(5) - 1) / 2
-        fn = lambda y: math.sin(y) + (xv - y) ** 2 / (2 * t)
+        fn = lambda y: amp * math.sin(y) + (xv - y) ** 2 / (2 * t)
         c, d_ = b - g * (b - a), a + g * (b - a)
         for _ in range(80):
             if fn(c) < fn(d_):

@@ -17,7 +17,8 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsc.so")
+# SC_LIBRARY_PATH selects another build of the same library (the sanitizer build of the tests)
+LIB_PATH = os.environ.get("SC_LIBRARY_PATH") or os.path.join(_HERE, "libsc.so")
 
 SC_OK, SC_ERR_ARG, SC_ERR_SHAPE, SC_ERR_UNSUPPORTED, SC_ERR_WORKSPACE, SC_ERR_DEVICE = 0, -1, -2, -3, -4, -5
 SC_F64, SC_F32_MIXED = 0, 1
@@ -64,10 +65,12 @@ class sc_batch_item(ctypes.Structure):
 
 class sc_hj_params(ctypes.Structure):
     _fields_ = [("beta", c_double), ("cfl", c_double), ("t_end", c_double), ("theta", c_double),
-                ("weights", c_int32), ("reserved", c_int32)]
+                ("weights", c_int32), ("hamiltonian", c_int32)]
 
 
 HJ_WEIGHTS = {"linear": 0, "wenoz": 1, "learned": 2}
+# "quadratic": u_t + (u_x^2 + u_y^2)/2 = 0; "ex3": Example 3, u_t + (1 + u_x + u_y)^2/2 = S (manufactured)
+HJ_HAMILTONIANS = {"quadratic": 0, "ex3": 1}
 
 
 @dataclass
@@ -465,11 +468,12 @@ def _f32dev(t, name, shape_last=None):
 
 
 class HJSolver:
-    """u_t + |grad u|^2 / 2 = 0 on a periodic n x n grid of [0, L]^2 (``sc_hj_*``); u is an (n1, n0)
-    float64 device tensor updated in place."""
+    """u_t + H(u_x, u_y) = S on a periodic n x n grid of [0, L]^2 (``sc_hj_*``): ``hamiltonian``
+    "quadratic" (|grad u|^2 / 2, S = 0) or "ex3" (Example 3 with its manufactured source); u is an
+    (n1, n0) float64 device tensor updated in place."""
 
     def __init__(self, n, L=2 * 3.141592653589793, beta=1.0, cfl=1.0, t_end=1.0, weights="linear",
-                 theta=0.05, device="cuda"):
+                 theta=0.05, device="cuda", hamiltonian="quadratic"):
         import torch
 
         n0, n1 = (n, n) if isinstance(n, int) else n
@@ -477,7 +481,7 @@ class HJSolver:
         self._gc = self.grid.c()
         self.p = sc_hj_params()
         self.p.beta, self.p.cfl, self.p.t_end, self.p.theta = beta, cfl, t_end, theta
-        self.p.weights, self.p.reserved = HJ_WEIGHTS[weights], 0
+        self.p.weights, self.p.hamiltonian = HJ_WEIGHTS[weights], HJ_HAMILTONIANS[hamiltonian]
         lib = load()
         nb = int(lib.sc_hj_workspace_bytes(ctypes.byref(self._gc)))
         if nb == 0:

@@ -119,10 +119,14 @@ int pick_variant(bool contig, int64_t n, int elem)
     return 6;  // 16 lines x 1024
 }
 
-bool pipe_enabled()
+// SC_PIPE=0: never the pipelined strided form; SC_PIPE=1: wherever its shape conditions hold;
+// unset: where it measured faster (see run_pass)
+int pipe_mode()
 {
     const char *env = std::getenv("SC_PIPE");
-    return !(env && env[0] == '0');
+    if (env && env[0] == '0') return 0;
+    if (env && env[0] == '1') return 1;
+    return 2;
 }
 
 // decay from the start of the last real wave-part of a tile to the tile's last real point
@@ -190,6 +194,7 @@ void fill_op(scx::OpArgs *P, int op, int order, double alpha, const Axis &ax, in
     const double x = nu * (double)ax.ncells;  // alpha (b - a)
     P->mu = std::exp(-x);
     P->inv1mmu = 1.0 / (-std::expm1(-x));
+    P->dir2inv = 2.0 / (1.0 - P->mu * P->mu);
     P->scale = scale;
     P->op = op;
     P->k = k;
@@ -265,11 +270,15 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     static const char *const kApply[3] = {"line_pass_apply_x", "line_pass_apply_y", "line_pass_apply_z"};
     hipError_t e;
     if (a.nchunks == 1) {
-        // strided lines of exactly one tile whose tiles are adjacent, aligned lines: the pipelined
-        // persistent form (SC_PIPE=0 turns it off, for comparisons)
+        // Strided lines of exactly one tile whose tiles are adjacent, aligned lines: the pipelined
+        // persistent form, where it measured faster (512^3, per pass): FP32 always (0.40 -> 0.35
+        // ms: its arithmetic is the longer part and now overlaps the loads), FP64 with one operator
+        // on lines strided by 1 MiB or more (z: 0.57 -> 0.55 ms; y, 4 KiB apart, 0.47 -> 0.48 ms;
+        // with two operators the pipelined FP64 kernel spills).  SC_PIPE overrides (pipe_mode).
         const scx::Variant &V = scx::variant(vid);
         const bool pipe = !V.contig && !multi && scx::pipe_variant(vid, elem) && ax.n == V.C() && ax.nlines % V.TC == 0 &&
-                          ax.stride % V.TC == 0 && ((uintptr_t)v & 15) == 0 && pipe_enabled();
+                          ax.stride % V.TC == 0 && ((uintptr_t)v & 15) == 0 && pipe_mode() != 0 &&
+                          (pipe_mode() == 1 || elem == 4 || (nops == 1 && ax.stride * elem >= (int64_t(1) << 20)));
         e = timed(kFused[dim], st, [&](const char **) {
             return pipe ? scx::launch_line_pass_pipe(a, elem, order, vid, st)
                         : scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
@@ -416,7 +425,7 @@ size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k)
     return b + 256;
 }
 
-sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, double alpha, const double *dirichlet_g,
+sc_status sc_apply_invL(const sc_grid *grid, int dim, int op, int order, double alpha, const double *dirichlet_g,
                         const void *v, void *out, void *ws, size_t ws_bytes, sc_stream_t stream)
 {
     sc_status s = check_line_args(grid, dim, order, alpha);
@@ -431,7 +440,7 @@ sc_status sc_apply_invL(const sc_grid *grid, int dim, sc_op op, int order, doubl
                     (hipStream_t)stream);
 }
 
-sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, sc_op op, int order, double alpha, int k,
+sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order, double alpha, int k,
                                  double scale, const double *dirichlet_g, const void *v, void *out, void *ws,
                                  size_t ws_bytes, sc_stream_t stream)
 {
@@ -553,7 +562,7 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
             if (lin(1.0, v, 0.0, v, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
             for (int d = 0; d < grid->ndim; ++d)
                 for (int k = 0; k < nops[d]; ++k) {
-                    sc_status r = sc_apply_D_partial_sum(grid, d, (sc_op)ops[d][k].op, pde->order, ops[d][k].alpha, stages,
+                    sc_status r = sc_apply_D_partial_sum(grid, d, ops[d][k].op, pde->order, ops[d][k].alpha, stages,
                                                          ops[d][k].scale, nullptr, v, TMP, psw, psw_bytes, stream);
                     if (r != SC_OK) return r;
                     if (lin(1.0, o, 1.0, TMP, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");

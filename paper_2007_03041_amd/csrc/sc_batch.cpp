@@ -422,9 +422,9 @@ sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *o
         char *oi = (char *)out + (size_t)it.offset * plan->elem;
         const double *gi = it.g_offset >= 0 ? g + it.g_offset : nullptr;
         if (it.k == 0)
-            s = sc_apply_invL(&gr, 0, (sc_op)it.op, plan->order, it.alpha, gi, vi, oi, ws, ws_bytes, stream);
+            s = sc_apply_invL(&gr, 0, it.op, plan->order, it.alpha, gi, vi, oi, ws, ws_bytes, stream);
         else
-            s = sc_apply_D_partial_sum(&gr, 0, (sc_op)it.op, plan->order, it.alpha, 1, it.scale, gi, vi, oi, ws, ws_bytes,
+            s = sc_apply_D_partial_sum(&gr, 0, it.op, plan->order, it.alpha, 1, it.scale, gi, vi, oi, ws, ws_bytes,
                                        stream);
         if (s != SC_OK) return s;
     }

@@ -29,6 +29,7 @@ struct OpArgs {
     double dlp_last;        //   last real point: full tile (or whole line) / last chunk of a line
     double inv1mmu;         // 1 / (1 - mu), mu = e^{-alpha (b - a)}
     double mu;
+    double dir2inv;         // 2 / (1 - mu^2): the 2x2 end-value system of L_0 on Dirichlet lines
     double scale;           // result multiplier
     int32_t op;             // 0 = L_L^{-1}, 1 = L_R^{-1}, 2 = L_0^{-1}
     int32_t k;              // 0: result is L^{-1}[v]; k >= 1: result is sum_{p=1..k} D^p[v]

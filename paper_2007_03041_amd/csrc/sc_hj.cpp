@@ -68,6 +68,7 @@ sc_status check_hj(const sc_grid *g, const sc_hj_params *p)
         return fail(SC_ERR_ARG, "beta and cfl must be finite and > 0");
     if (!(p->t_end >= 0.0)) return fail(SC_ERR_ARG, "t_end must be >= 0");
     if (p->weights < 0 || p->weights > 2) return fail(SC_ERR_ARG, "weights must be 0, 1 or 2");
+    if (p->hamiltonian < 0 || p->hamiltonian > 1) return fail(SC_ERR_ARG, "hamiltonian must be 0 or 1");
     if (!(p->theta >= 0.0)) return fail(SC_ERR_ARG, "theta must be >= 0");
     const double h = std::min(axis_of(g, 0).dx, axis_of(g, 1).dx);
     const double alpha = p->beta / (p->cfl * h);
@@ -88,6 +89,8 @@ HjStepArgs step_args(const sc_grid *g, const sc_hj_params *p)
     A.alpha_x = A.alpha_y = p->beta / (p->cfl * h);
     A.cfl_h = p->cfl * h;
     A.t_end = p->t_end;
+    A.hamiltonian = p->hamiltonian;
+    A.pad_ = 0;
     return A;
 }
 

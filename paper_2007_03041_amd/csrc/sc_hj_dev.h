@@ -33,12 +33,16 @@ struct HjQuadArgs {
     double theta;    // largest accepted |proposal - WENO-Z| per weight
 };
 
+enum { HJ_H_QUADRATIC = 0, HJ_H_EX3 = 1 };
+
 struct HjStepArgs {
     int64_t nx, ny, npts;
     double dx, dy;
     double alpha_x, alpha_y;
     double cfl_h;  // CFL min(dx, dy): dt = cfl_h / c
     double t_end;
+    int32_t hamiltonian;  // HJ_H_QUADRATIC: (p^2 + q^2) / 2; HJ_H_EX3: (1 + p + q)^2 / 2 - S(x, y, t)
+    int32_t pad_;
 };
 
 hipError_t launch_hj_weno_quad(int mode, const double *u, double *JL, double *JR, const HjQuadArgs &A,

@@ -341,9 +341,25 @@ __global__ void __launch_bounds__(256) hj_update(double *__restrict__ u, const d
         const double pm = A.alpha_x * DmX[p], pp = -A.alpha_x * DpX[p];
         const double qm = A.alpha_y * DmY[p], qp = -A.alpha_y * DpY[p];
         const double px = 0.5 * (pm + pp), qy = 0.5 * (qm + qp);
-        const double H = 0.5 * (px * px + qy * qy) + c * 0.5 * (pm - pp) + c * 0.5 * (qm - qp);
+        double H;
+        if (A.hamiltonian == HJ_H_EX3) {
+            // Example 3 (Sec. 5.1): H = (1 + p + q)^2 / 2 and the source of the manufactured
+            // solution u = t (sin x + sin y), S = sin x + sin y + (1 + t cos x + t cos y)^2 / 2,
+            // at the old time; the wave speed is the largest |H_p| = |1 + p + q| over the four
+            // one-sided combinations
+            const double s = 1.0 + px + qy;
+            const double t = state[HJ_S_T];
+            const double x = (double)(p % A.nx) * A.dx, y = (double)(p / A.nx) * A.dy;
+            const double sx = sin(x), sy = sin(y);
+            const double w = 1.0 + t * cos(x) + t * cos(y);
+            const double S = sx + sy + 0.5 * w * w;
+            H = 0.5 * s * s + c * 0.5 * (pm - pp) + c * 0.5 * (qm - qp) - S;
+            m = fmax(fmax(fabs(1.0 + pm + qm), fabs(1.0 + pm + qp)), fmax(fabs(1.0 + pp + qm), fabs(1.0 + pp + qp)));
+        } else {
+            H = 0.5 * (px * px + qy * qy) + c * 0.5 * (pm - pp) + c * 0.5 * (qm - qp);
+            m = fmax(fmax(fabs(pm), fabs(pp)), fmax(fabs(qm), fabs(qp)));
+        }
         u[p] = u[p] - dt * H;
-        m = fmax(fmax(fabs(pm), fabs(pp)), fmax(fabs(qm), fabs(qp)));
     }
     red[tid] = m;
     __syncthreads();
@@ -354,7 +370,7 @@ __global__ void __launch_bounds__(256) hj_update(double *__restrict__ u, const d
     if (tid == 0) part[blockIdx.x] = red[0];
 }
 
-// Initial wave speed: max over periodic central differences of u0 along both axes.
+// Initial wave speed: max of |H_p|, |H_q| at periodic central differences of u0.
 __global__ void __launch_bounds__(256) hj_init_speed(const double *__restrict__ u, const HjStepArgs A,
                                                      double *__restrict__ part)
 {
@@ -368,7 +384,7 @@ __global__ void __launch_bounds__(256) hj_init_speed(const double *__restrict__ 
         const int64_t jp = j + 1 == A.ny ? 0 : j + 1, jm = j == 0 ? A.ny - 1 : j - 1;
         const double gx = (u[j * A.nx + ip] - u[j * A.nx + im]) / (2.0 * A.dx);
         const double gy = (u[jp * A.nx + i] - u[jm * A.nx + i]) / (2.0 * A.dy);
-        m = fmax(fabs(gx), fabs(gy));
+        m = A.hamiltonian == HJ_H_EX3 ? fabs(1.0 + gx + gy) : fmax(fabs(gx), fabs(gy));
     }
     red[tid] = m;
     __syncthreads();

@@ -303,9 +303,8 @@ __device__ __forceinline__ void boundary_constants(const OA &P, int bc, double I
         Bp = gb;
     } else {
         const double r0 = ga - 0.5 * IL0, r1 = gb - 0.5 * IRn;
-        const double det = 1.0 - P.mu * P.mu;
-        Ap = 2.0 * (r0 - P.mu * r1) / det;
-        Bp = 2.0 * (r1 - P.mu * r0) / det;
+        Ap = (r0 - P.mu * r1) * P.dir2inv;
+        Bp = (r1 - P.mu * r0) * P.dir2inv;
     }
 }
 

@@ -43,7 +43,7 @@ sc_status scratch_ptr(void **out)
 
 }  // namespace
 
-extern "C" sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, sc_op op, int order, double alpha,
+extern "C" sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, int op, int order, double alpha,
                                            const double *dirichlet_g, const void *v, void *out, sc_stream_t stream)
 {
     using namespace scx::host;

@@ -117,10 +117,11 @@ def test_mlp_gradients_match_oracle(gpu_lib):
         bound = (2 * kappa + n * F32_EPS) * mag + 1e-12
         d = np.abs(gg[k] - g[k])
         assert (d <= bound).all(), (k, float((d / bound).max()))
-        frac_tight.append(float((d <= 1e-3 * mag + 1e-12).mean()))
+        frac_tight.append(float((d <= 1e-5 * mag + 1e-12).mean()))
         print(f"gradients {k}: max |diff| / magnitude {float((d / (mag + 1e-30)).max()):.2e}")
-    print("gradients: fraction of elements within 1e-3 of their magnitude:", frac_tight)
-    assert min(frac_tight) > 0.9
+    # where no BF16 rounding differs (nearly everywhere) the two agree to the FP32 sums
+    print("gradients: fraction of elements within 1e-5 of their magnitude:", frac_tight)
+    assert min(frac_tight) > 0.99
 
 
 def test_adam_steps_match_oracle(gpu_lib):
@@ -167,6 +168,38 @@ def test_solver_matches_oracle(gpu_lib, weights, T):
     assert st["steps"] == len(hist) and abs(st["t"] - T) < 1e-12
     got = u.cpu().numpy()
     assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_example3_matches_oracle(gpu_lib):
+    """Example 3 of Sec. 5.1 (H = (1 + u_x + u_y)^2 / 2 with the manufactured source, u0 = 0, T = 0.5,
+    linear weights): the GPU solver against the oracle's per-axis adaptive rule, which here takes
+    the same steps (the two speeds are equal), to 1e-10."""
+    n, T = 64, 0.5
+    ref, hist = hj.hj_run_general(np.zeros((n, n)), L, T, kind="ex3", source=hj.example3_source)
+    s = sc.HJSolver(n, L=L, t_end=T, weights="linear", hamiltonian="ex3")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    s.run_to(u)
+    st = s.read_state()
+    assert st["steps"] == len(hist) and abs(st["t"] - T) < 1e-12
+    assert abs(st["c"] - hist[-1][2]) < 1e-10 * hist[-1][2]
+    assert np.abs(u.cpu().numpy() - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_example3_converges_first_order_on_gpu(gpu_lib):
+    """Example 3 on the GPU from 128^2 to 1024^2: the error against u = t (sin x + sin y) at T = 0.5
+    falls at first order (the explicit Euler step of Sec. 2.5)."""
+    T = 0.5
+    errs = []
+    for n in (128, 256, 512, 1024):
+        s = sc.HJSolver(n, L=L, t_end=T, weights="linear", hamiltonian="ex3")
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        s.run_to(u)
+        x = torch.arange(n, dtype=torch.float64, device="cuda") * (L / n)
+        exact = T * (torch.sin(x)[None, :] + torch.sin(x)[:, None])
+        errs.append((u - exact).abs().max().item())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    print("Example 3 errors", errs, "rates", rates)
+    assert all(r > 0.8 for r in rates[1:]) and 0.9 < rates[-1] < 1.2, rates
 
 
 def test_harvest_matches_oracle(gpu_lib):

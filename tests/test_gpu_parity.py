@@ -482,10 +482,12 @@ PIPE_CASES = [
 
 
 @pytest.mark.parametrize("n,dim,bc,order", PIPE_CASES)
-def test_pipelined_strided_whole_line_passes(gpu_lib, n, dim, bc, order):
+def test_pipelined_strided_whole_line_passes(gpu_lib, n, dim, bc, order, monkeypatch):
     """Strided passes whose lines fill one tile run persistent, their tiles loaded straight into LDS
-    while the previous tile is finished: every operator against the oracle, with Dirichlet values."""
+    while the previous tile is finished (SC_PIPE=1: wherever the shape allows, not only where it
+    is the faster form): every operator against the oracle, with Dirichlet values."""
     sc = gpu_lib
+    monkeypatch.setenv("SC_PIPE", "1")
     v = W.random_field((n[2], n[1], n[0]), index=97 + dim)
     g = Grid(n, (0.0, 0.0, 0.0), (1.0, 2.0, 3.0), (bc, bc, bc))
     alpha = 0.07 / g.dx(dim)
@@ -500,10 +502,13 @@ def test_pipelined_strided_whole_line_passes(gpu_lib, n, dim, bc, order):
     assert err(got, ref, 2.5 * np.abs(v).max()) < TOL
 
 
-def test_pipelined_passes_two_operators_in_a_time_step(gpu_lib):
+@pytest.mark.parametrize("pipe", ["1", ""])
+def test_pipelined_passes_two_operators_in_a_time_step(gpu_lib, pipe, monkeypatch):
     """Advection and diffusion in one pass (two operators) on 512-point y and z lines, split steps
-    with the last pass in place."""
+    with the last pass in place; the pipelined form forced, and the default choice."""
     sc = gpu_lib
+    if pipe:
+        monkeypatch.setenv("SC_PIPE", pipe)
     n = (48, 512, 512)
     u0 = W.random_field((n[2], n[1], n[0]), index=99)
     g = Grid(n, (0, 0, 0), (1.0, 4.0, 4.0))
@@ -521,6 +526,7 @@ def test_pipelined_and_tiled_passes_agree_bitwise(gpu_lib, monkeypatch):
     n = (64, 512, 40)
     v = dev(W.random_field((n[2], n[1], n[0]), index=98))
     g = Grid(n, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ("dirichlet",) * 3)
+    monkeypatch.setenv("SC_PIPE", "1")
     a = host(sc.apply_invL(v, g, 1, "0", 6, 30.0)).copy()
     monkeypatch.setenv("SC_PIPE", "0")
     b = host(sc.apply_invL(v, g, 1, "0", 6, 30.0))

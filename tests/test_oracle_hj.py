@@ -256,3 +256,54 @@ def test_adam_decreases_the_loss_on_a_fixed_batch():
         om, c = mlp.forward(p, X)
         mlp.adam_step(p, mlp.backward(p, c, T), st, 3e-3)
     assert mlp.loss(mlp.forward(p, X)[0], T) < 0.5 * l0
+
+
+# ------------------------------------------------------------------------------ Example 3, per-axis speeds
+def test_example3_manufactured_solution_converges_first_order():
+    """Sec. 5.1, Example 3: u_t + (1 + u_x + u_y)^2 / 2 = S on [0, 2 pi]^2, u0 = 0, T = 0.5, linear
+    weights, the adaptive rule with the lagged wave speeds; with the source of the manufactured
+    solution u = t (sin x + sin y) the error falls at first order (the Euler step), and the tracked
+    wave speed approaches max |1 + u_x + u_y| = 1 + 2T."""
+    L, T = 2 * math.pi, 0.5
+    errs = []
+    for n in (64, 128, 256):
+        u, hist = hj.hj_run_general(np.zeros((n, n)), L, T, cfl=1.0, kind="ex3", source=hj.example3_source)
+        x = np.arange(n) * (L / n)
+        exact = T * (np.sin(x)[None, :] + np.sin(x)[:, None])
+        errs.append(np.abs(u - exact).max())
+        assert abs(hist[-1][0] - T) < 1e-14
+        assert abs(hist[-1][2] - (1 + 2 * T)) < 0.05 * (1 + 2 * T)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert errs[0] > errs[1] > errs[2]
+    assert 0.8 < rates[-1] < 1.3, rates
+    assert errs[-1] < 0.015
+
+
+def test_per_axis_speeds_reduce_to_the_symmetric_rule():
+    """With equal speeds on equal spacings (u0 = sin x + sin y) the per-axis rule takes the same
+    steps, alpha and dissipation as the one-speed rule, so the two runs agree to rounding."""
+    L, T, n = 2 * math.pi, 0.75, 48
+    x = np.arange(n) * (L / n)
+    u0 = np.sin(x)[None, :] + np.sin(x)[:, None]
+    a, ha = hj.hj_run(u0, L, T, mode="linear")
+    b, hb = hj.hj_run_general(u0, L, T, kind="quadratic", mode="linear")
+    assert len(ha) == len(hb)
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_per_axis_speeds_on_unequal_speeds_follow_hopf_lax():
+    """u0 = sin x + 0.3 sin y: the x speed is about three times the y speed; the per-axis rule
+    (dt from the faster axis, alpha_y = beta / (c_y dt)) converges to the separable Hopf-Lax
+    solution w_1(x, t) + w_{0.3}(y, t) before kinks form, and its y speed tracks max |u_y|."""
+    L, T = 2 * math.pi, 0.5
+    errs = []
+    for n in (32, 64, 128):
+        x = np.arange(n) * (L / n)
+        u0 = np.sin(x)[None, :] + 0.3 * np.sin(x)[:, None]
+        u, hist = hj.hj_run_general(u0, L, T, kind="quadratic", mode="linear")
+        exact = hj.hopf_lax_1d(x, T)[None, :] + hj.hopf_lax_1d(x, T, amp=0.3)[:, None]
+        errs.append(np.abs(u - exact).max())
+        cx, cy = hist[-1][2], hist[-1][3]
+        assert 2.5 < cx / cy < 4.0
+    assert errs[0] > errs[1] > errs[2]
+    assert math.log2(errs[1] / errs[2]) > 0.7
