@@ -230,6 +230,29 @@ int64_t nchunks_for(const Axis &ax, int elem)
 
 // chunked passes with at most this many chunks per line form their carries inside the apply launch
 constexpr int64_t kFuseCarryChunks = 16;
+// ... and with at most this many run as one single-pass launch (the gathered totals sit in registers)
+constexpr int64_t kSingleChunks = 8;
+
+// SC_SINGLE=0 selects the two-launch form (aggregate, then apply) for every chunked pass
+bool single_pass_enabled()
+{
+    const char *env = std::getenv("SC_SINGLE");
+    return !(env && env[0] == '0');
+}
+
+// polls of the other chunks' totals before a single-pass tile gives up and writes NaN (SC_SPIN_LIMIT;
+// each poll sleeps about 128 cycles, so the default bound is about a quarter second).  A negative
+// value -m makes every tile ignore the published totals and give up after m polls: a host-side way
+// for tests to exercise the give-up path without any wait that cannot end.
+int spin_limit()
+{
+    const char *env = std::getenv("SC_SPIN_LIMIT");
+    if (env && *env) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v > -(1L << 30) && v < (1L << 30)) return (int)v;
+    }
+    return 1 << 22;
+}
 
 // One pass along `dim`: out = acc_term + sum_ops scale * result(op).
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v,
@@ -291,6 +314,23 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     const int64_t ent = (int64_t)nops * ax.nlines * a.nchunks;
     a.agg = (double *)wsp;
     a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
+    if (a.nchunks <= kSingleChunks && single_pass_enabled()) {
+        // lines of at most 8 chunks: one launch reads the field once; its tiles publish their chunk
+        // totals and gather those of the other chunks of their lines (the slots and the claim
+        // counter are reset first, by a kernel on the same stream)
+        static const char *const kSingle[3] = {"line_pass_single_x", "line_pass_single_y", "line_pass_single_z"};
+        a.sync = (uint32_t *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
+        a.spin_limit = spin_limit();
+        e = timed("single_pass_reset", st, [&](const char **) {
+            return scx::launch_single_pass_reset(a.agg, 3 * ent, a.sync, st);
+        });
+        if (e == hipSuccess)
+            e = timed(kSingle[dim], st, [&](const char **) {
+                return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_SINGLE, false, st);
+            });
+        if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        return SC_OK;
+    }
     // lines of few chunks: every apply tile forms its own carries from the chunk totals (one launch
     // less); longer lines go through the carry launch
     a.fuse_carry = a.nchunks <= kFuseCarryChunks ? 1 : 0;

@@ -62,6 +62,9 @@ struct PassArgs {
     int32_t acc_mode;       // 0 none, 1 add the operand v, 2 add acc
     int32_t nops;           // 1 or 2
     int32_t fuse_carry;     // chunked apply: each tile forms its chunk carries from the aggregates
+    uint32_t *sync;         // single-pass chunked launches: the tile claim counter
+    int32_t spin_limit;     // single-pass: polls of the other chunks' totals before a tile gives up
+    int32_t pad_;
     // Dirichlet ends: the one-sided stencils of the order/2 points nearest an end integrate the
     // interpolant through the `order` end values; extending the line by that interpolant's values
     // at m = 1..order/2 points beyond the end makes the centred interior stencil integrate the same

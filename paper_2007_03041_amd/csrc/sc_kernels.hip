@@ -219,6 +219,22 @@ hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int
                 : launch_line_pass_t<float, 6, false>(a, vid, mode, multi, st);
 }
 
+// Resets the chunk totals of a single-pass chunked launch to "not yet published" and its claim
+// counter to 0 (a kernel rather than a memset, so the pair can sit in a captured graph).
+__global__ void __launch_bounds__(256) single_pass_reset(double *__restrict__ agg, int64_t n, uint32_t *sync)
+{
+    const double e = __longlong_as_double((long long)CHUNK_EMPTY);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) agg[i] = e;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sync = 0u;
+}
+
+hipError_t launch_single_pass_reset(double *agg, int64_t n, uint32_t *sync, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(single_pass_reset, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, agg, n, sync);
+    return hipGetLastError();
+}
+
 bool pipe_variant(int vid, int elem) { return (vid == 5 && elem == 8) || vid == 12; }
 
 hipError_t launch_line_pass_pipe(const PassArgs &a, int elem, int order, int vid, hipStream_t st)

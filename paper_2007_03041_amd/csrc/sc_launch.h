@@ -7,7 +7,7 @@
 
 namespace scx {
 
-enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2 };
+enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2, LMODE_SINGLE = 3 };
 
 int num_variants();
 const Variant &variant(int id);
@@ -17,6 +17,8 @@ bool variant_built(int vid, int elem);
 // elem = 8 (FP64) or 4 (FP32 data, mixed-precision carries)
 hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int mode, bool multi, hipStream_t st);
 hipError_t launch_chunk_carry(const PassArgs &a, hipStream_t st);
+// resets the chunk totals (n doubles) and the claim counter of a single-pass chunked launch
+hipError_t launch_single_pass_reset(double *agg, int64_t n, uint32_t *sync, hipStream_t st);
 // Pipelined strided pass (variants 5 and 12; lines of exactly C points, line count and stride
 // multiples of TC, operand 16-byte aligned): see line_pass_pipe.
 hipError_t launch_line_pass_pipe(const PassArgs &a, int elem, int order, int vid, hipStream_t st);

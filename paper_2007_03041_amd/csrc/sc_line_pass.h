@@ -52,7 +52,20 @@
 
 namespace scx {
 
-enum { MODE_FUSED = 0, MODE_AGG = 1, MODE_APPLY = 2 };
+enum { MODE_FUSED = 0, MODE_AGG = 1, MODE_APPLY = 2, MODE_SINGLE = 3 };
+
+// Single-pass chunked launches: the chunk totals slots hold this bit pattern (a signalling NaN, which
+// arithmetic never produces) until their tile publishes them.
+constexpr uint64_t CHUNK_EMPTY = 0x7FF4DEADBEEF0001ull;
+__device__ __forceinline__ bool chunk_empty(double x) { return (uint64_t)__double_as_longlong(x) == CHUNK_EMPTY; }
+__device__ __forceinline__ void publish_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double read_agent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <typename R>
 __device__ __forceinline__ R shfl_up_r(R x, int delta)
@@ -626,10 +639,19 @@ line_pass(const PassArgs a)
     constexpr bool pipe_first = false;
     constexpr int64_t pipe_next = -1;
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
-    const int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    if constexpr (MODE == MODE_SINGLE) {
+        // tiles are claimed in order (line group by line group, its chunks in turn), so every tile
+        // a tile waits for has been claimed by a running workgroup or will be by the next one to start
+        __shared__ uint32_t claim_s;
+        if (threadIdx.x == 0) claim_s = atomicAdd(a.sync, 1u);
+        __syncthreads();
+        blk = claim_s;
+    }
     const int tid_in = threadIdx.x;
 #include "sc_line_pass_body.inc"
 }
+
 
 // Persistent strided pass over whole lines (y/z lines that fit one tile): workgroup b takes line
 // tiles b, b + grid, ...  Each tile's operand goes straight from memory to LDS; the loads of the
@@ -727,6 +749,9 @@ static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStrea
         const dim3 grid(tiles * a.nchunks);
         if (mode == MODE_AGG)
             hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, NOPS, false, FULL>), grid, dim3(NT), 0, st, a);
+        else if (mode == MODE_SINGLE)
+            hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_SINGLE, NT, NOPS, false, FULL>), grid, dim3(NT), 0,
+                               st, a);
         else
             hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, NOPS, false, FULL>), grid, dim3(NT), 0, st,
                                a);

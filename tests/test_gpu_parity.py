@@ -531,3 +531,49 @@ def test_pipelined_and_tiled_passes_agree_bitwise(gpu_lib, monkeypatch):
     monkeypatch.setenv("SC_PIPE", "0")
     b = host(sc.apply_invL(v, g, 1, "0", 6, 30.0))
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------------------ single-pass chunked lines
+SINGLE_CASES = [
+    ((256, 4096), 1, "periodic", 4),     # y lines of 8 chunks (the 4096^2 workload's y pass, fewer lines)
+    ((20000, 6), 0, "dirichlet", 6),     # x lines of 3 chunks, ragged
+    ((48, 2200, 3), 1, "dirichlet", 6),  # y lines of 5 chunks, ragged
+    ((40, 3, 1700), 2, "periodic", 4),   # z lines of 4 chunks, ragged
+]
+
+
+@pytest.mark.parametrize("n,dim,bc,order", SINGLE_CASES)
+def test_single_pass_chunked_lines(gpu_lib, n, dim, bc, order, monkeypatch):
+    """Lines of 2..8 chunks in one launch (each tile publishes its chunk totals and gathers the
+    others'): against the oracle, and bit for bit against the aggregate + apply launches."""
+    sc = gpu_lib
+    v = W.random_field(tuple(reversed(n)), index=71 + dim)
+    g = Grid(n, tuple(0.0 for _ in n), tuple(1.0 + e for e in range(len(n))), tuple(bc for _ in n))
+    lines = v.size // n[dim]
+    gv = np.random.default_rng(3).uniform(-1, 1, (lines, 2)) if bc == "dirichlet" else None
+    for op, nu in (("0", 0.03), ("R", 1.0), ("L", 0.2)):
+        alpha = nu / g.dx(dim)
+        ref = oracle.apply_invL(ogrid(g), dim, op, order, alpha, v, gv)
+        got = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv))).copy()
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+        monkeypatch.setenv("SC_SINGLE", "0")
+        two = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv)))
+        monkeypatch.delenv("SC_SINGLE")
+        assert np.array_equal(got, two), op
+
+
+def test_single_pass_bounded_wait_gives_up_with_nan(gpu_lib, monkeypatch):
+    """The gather's wait is bounded: forced from the host to give up (SC_SPIN_LIMIT=-m: published
+    totals are ignored, m polls), every tile of a chunked line writes NaN and the launch ends; the
+    next call, with the default limit, is correct again."""
+    sc = gpu_lib
+    n = (128, 4096)
+    v = W.random_field((n[1], n[0]), index=72)
+    g = Grid(n)
+    monkeypatch.setenv("SC_SPIN_LIMIT", "-3")
+    out = host(sc.apply_invL(dev(v), g, 1, "0", 4, 40.0))
+    assert np.isnan(out).all()
+    monkeypatch.delenv("SC_SPIN_LIMIT")
+    ref = oracle.apply_invL(ogrid(g), 1, "0", 4, 40.0, v)
+    got = host(sc.apply_invL(dev(v), g, 1, "0", 4, 40.0))
+    assert err(got, ref, np.abs(ref).max()) < TOL
