@@ -211,3 +211,21 @@ def test_pipelined_strided_passes_mixed(gpu_lib, n, dim, bc):
         ref = oracle.apply_invL(ogrid(g), dim, op, 6, alpha, v, gv)
         got = host(sc.apply_invL(dev32(v), mixed(g), dim, op, 6, alpha, g=None if gv is None else dev64(gv)))
         assert err(got, ref, np.abs(ref).max()) < TOL, op
+
+
+@pytest.mark.parametrize("mu", [0.95, 0.6, 0.45, 0.2, 1e-3])
+def test_dirichlet_L0_end_constants_mixed(gpu_lib, mu):
+    """L_0^{-1} on Dirichlet lines with random end values, alpha (b - a) = -ln mu: for mu near 1 the
+    2x2 end-value constants exceed the result and cancel in it (they are summed per point in FP64);
+    for mu <= 1/2 they ride through the FP32 sweeps.  Both within 1e-5 of the oracle, along x, y, z."""
+    sc = gpu_lib
+    n = (300, 40, 33)
+    v = W.random_field((n[2], n[1], n[0]), index=160)
+    g = Grid(n, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ("dirichlet",) * 3)
+    for dim in range(3):
+        alpha = -math.log(mu)  # (b - a) = 1
+        lines = v.size // n[dim]
+        gv = np.random.default_rng(dim).uniform(-1, 1, (lines, 2))
+        ref = oracle.apply_invL(ogrid(g), dim, "0", 6, alpha, v, gv)
+        got = host(sc.apply_invL(dev32(v), mixed(g), dim, "0", 6, alpha, g=dev64(gv)))
+        assert err(got, ref, np.abs(ref).max()) < TOL, dim
