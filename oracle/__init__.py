@@ -104,11 +104,15 @@ def _load():
         lib.sco_apply_D_partial_sum.argtypes = [gp, c_int, c_int, c_int, c_double, c_int,
                                                 c_double, dp, dp, dp]
         lib.sco_time_step.argtypes = [gp, POINTER(_Pde), c_int, dp]
+        lib.sco_line_invL_nn.argtypes = [c_int, c_int, c_int, c_double, c_double, c_int64, c_int64, dp,
+                                         c_double, c_double, dp]
+        lib.sco_apply_invL_nn.argtypes = [gp, c_int, c_int, c_int, c_double, c_int64, dp, dp, dp]
         lib.sco_num_threads.argtypes = []
         lib.sco_set_threads.argtypes = [c_int]
         for f in ("sco_weights", "sco_line_quad", "sco_line_sweep", "sco_line_invL",
                   "sco_local_quad", "sco_sweep_LR", "sco_apply_invL",
-                  "sco_apply_D_partial_sum", "sco_time_step", "sco_num_threads", "sco_set_threads"):
+                  "sco_apply_D_partial_sum", "sco_time_step", "sco_num_threads", "sco_set_threads",
+                  "sco_line_invL_nn", "sco_apply_invL_nn"):
             getattr(lib, f).restype = c_int
         _libs[_build_kind] = lib
         _lib = lib
@@ -216,6 +220,26 @@ def apply_invL(grid: _Grid, dim, op, order, alpha, v, g=None):
     _check(_load().sco_apply_invL(ctypes.byref(grid), dim, _OPS[op], order, alpha,
                                   _p(gv) if gv is not None else None, _p(v), _p(out)),
            "apply_invL")
+    return out
+
+
+def line_invL_nn(bc, op, order, alpha, dx, v, block, ga=0.0, gb=0.0):
+    """Nearest-neighbour block form of line_invL (Sec. 3): blocks of `block` points."""
+    v = _f64(v)
+    out = np.zeros_like(v)
+    _check(_load().sco_line_invL_nn(_BCS[bc], _OPS[op], order, alpha, dx, v.size, int(block), _p(v), ga, gb,
+                                    _p(out)), "line_invL_nn")
+    return out
+
+
+def apply_invL_nn(grid: _Grid, dim, op, order, alpha, v, block, g=None):
+    """line_invL_nn along every line of axis `dim` (blocks of `block` points)."""
+    v = _f64(v)
+    out = np.zeros_like(v)
+    gv = _gvals(g, v.size // grid.n[dim])
+    _check(_load().sco_apply_invL_nn(ctypes.byref(grid), dim, _OPS[op], order, alpha, int(block),
+                                     _p(gv) if gv is not None else None, _p(v), _p(out)),
+           "apply_invL_nn")
     return out
 
 

@@ -235,6 +235,87 @@ int sco_line_invL(int bc, int op, int order, double alpha, double dx, int64_t n,
     return rc;
 }
 
+/* Nearest-neighbour block form of one application of L_op^{-1} (Sec. 3).  The line is cut into
+ * blocks of `block` points (the last takes the remainder); block i holds the local integrals J of
+ * its own points.  Steps, in the order of Sec. 3:
+ *   1. the local integrals J_R, J_L with the global stencils (the quadrature halo of Sec. 3);
+ *   2. each block sweeps its own J from zero (the block-local integrals I_{R,i}, I_{L,i});
+ *   3. the N-N constants: block i > 0 receives A_i = the right-moving local integral of block i-1 at
+ *      their shared end, block i < last receives B_i = the left-moving local integral of block i+1
+ *      at their shared end (Sec. 3.2, the compact forms after the N-N criterion; the left-moving
+ *      one read as I_L of the next block);
+ *   4. the line constants: A acts on block 0 only and B on the last block only.  Periodic lines take
+ *      the periodic choice of Sec. 3.2: A = the last block's own right-moving integral at b (its
+ *      sweep continued over the wrapped cell), B = the first block's own left-moving integral at a.
+ *      Dirichlet lines impose the end values on the block operators at the end points, with the
+ *      coupling e^{-alpha (b - a)} of the two ends dropped (the line is at least one block long);
+ *   5. combine as in sco_line_invL, each block with its own constants (Sec. 3.2/3.3 block operators).
+ * The result equals sco_line_invL's within e^{-alpha L_m} max|I| when every block spans L_m with
+ * e^{-alpha L_m} <= eps (the N-N criterion, eq. (NN constraint general)). */
+int sco_line_invL_nn(int bc, int op, int order, double alpha, double dx, int64_t n, int64_t block,
+                     const double *v, double ga, double gb, double *out)
+{
+    if (op < 0 || op > 2 || block < 1) return -1;
+    double *JL = malloc(sizeof(double) * n), *JR = malloc(sizeof(double) * n);
+    double *IL = malloc(sizeof(double) * n), *IR = malloc(sizeof(double) * n);
+    int64_t nb = (n + block - 1) / block;
+    double *TR = malloc(sizeof(double) * nb), *TL = malloc(sizeof(double) * nb);
+    int rc = sco_line_quad(bc, order, alpha, dx, n, v, JL, JR);
+    if (rc == 0) {
+        double d = exp(-alpha * dx);
+        int64_t ncell = (bc == SCO_BC_PERIODIC) ? n : n - 1;
+        /* 2. block-local sweeps from zero; J_R[0] (periodic: the wrapped cell) stays out of the
+         *    sweeps as in the global form, J_L[n-1] is the wrapped cell or zero */
+        for (int64_t ib = 0; ib < nb; ++ib) {
+            int64_t s = ib * block, e = (s + block < n) ? s + block : n;
+            IR[s] = (s == 0) ? 0.0 : JR[s];
+            for (int64_t i = s + 1; i < e; ++i) IR[i] = d * IR[i - 1] + JR[i];
+            IL[e - 1] = (e == n) ? ((bc == SCO_BC_PERIODIC) ? JL[n - 1] : 0.0) : JL[e - 1];
+            for (int64_t i = e - 2; i >= s; --i) IL[i] = d * IL[i + 1] + JL[i];
+            TR[ib] = IR[e - 1];
+            TL[ib] = IL[s];
+        }
+        /* 3. the neighbours' block-end integrals, carried into each block */
+        for (int64_t ib = 0; ib < nb; ++ib) {
+            int64_t s = ib * block, e = (s + block < n) ? s + block : n;
+            double Ai = (ib > 0) ? TR[ib - 1] : 0.0;
+            double Bi = (ib < nb - 1) ? TL[ib + 1] : 0.0;
+            for (int64_t i = s; i < e; ++i) {
+                IR[i] += Ai * exp(-alpha * dx * (double)(i - s + 1));
+                IL[i] += Bi * exp(-alpha * dx * (double)(e - i));
+            }
+        }
+        /* 4. the line constants */
+        double A = 0.0, B = 0.0;
+        if (bc == SCO_BC_PERIODIC) {
+            double sc = (op == SCO_OP_0) ? 0.5 : 1.0;
+            A = sc * (d * TR[nb - 1] + JR[0]);
+            B = sc * TL[0];
+        } else if (op == SCO_OP_R) {
+            A = ga;
+        } else if (op == SCO_OP_L) {
+            B = gb;
+        } else {
+            A = ga - 0.5 * IL[0];
+            B = gb - 0.5 * IR[n - 1];
+        }
+        /* 5. combine */
+        int64_t last0 = (nb - 1) * block;
+        for (int64_t i = 0; i < n; ++i) {
+            double ea = (i < block) ? exp(-alpha * dx * (double)i) : 0.0;
+            double eb = (i >= last0) ? exp(-alpha * dx * (double)(ncell - i)) : 0.0;
+            if (op == SCO_OP_R)
+                out[i] = IR[i] + A * ea;
+            else if (op == SCO_OP_L)
+                out[i] = IL[i] + B * eb;
+            else
+                out[i] = 0.5 * (IL[i] + IR[i]) + A * ea + B * eb;
+        }
+    }
+    free(JL); free(JR); free(IL); free(IR); free(TR); free(TL);
+    return rc;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Whole arrays                                                                             */
 /* ---------------------------------------------------------------------------------------- */
@@ -346,6 +427,26 @@ int sco_apply_D_partial_sum(const sco_grid *g, int dim, int op, int order, doubl
             }
         }
         for (int64_t i = 0; i < n; ++i) out[b + i * s] = scale * acc[i];
+        free(buf);
+    }
+    return bad ? -2 : 0;
+}
+
+int sco_apply_invL_nn(const sco_grid *g, int dim, int op, int order, double alpha, int64_t block,
+                      const double *gvals, const double *v, double *out)
+{
+    if (!grid_ok(g, dim) || !(alpha > 0.0) || op < 0 || op > 2 || block < 1) return -1;
+    int64_t n = g->n[dim], s = axis_stride(g, dim), lines = total_points(g) / n;
+    double dx = axis_dx(g, dim);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t L = 0; L < lines; ++L) {
+        double *buf = malloc(sizeof(double) * 2 * n);
+        int64_t b = line_base(g, dim, L);
+        double ga = gvals ? gvals[2 * L] : 0.0, gb = gvals ? gvals[2 * L + 1] : 0.0;
+        for (int64_t i = 0; i < n; ++i) buf[i] = v[b + i * s];
+        bad |= (sco_line_invL_nn(g->bc[dim], op, order, alpha, dx, n, block, buf, ga, gb, buf + n) != 0);
+        for (int64_t i = 0; i < n; ++i) out[b + i * s] = buf[n + i];
         free(buf);
     }
     return bad ? -2 : 0;

@@ -56,6 +56,13 @@ int sco_line_sweep(int bc, double alpha, double dx, int64_t n, const double *JL,
 int sco_line_invL(int bc, int op, int order, double alpha, double dx, int64_t n, const double *v,
                   double ga, double gb, double *out);
 
+/* Nearest-neighbour block form of sco_line_invL (Sec. 3): blocks of `block` points sweep their own
+ * local integrals from zero and exchange only their block-end integrals with their neighbours;
+ * the line constants act on the end blocks only (periodic choice of Sec. 3.2; Dirichlet end
+ * values imposed on the end blocks' operators). */
+int sco_line_invL_nn(int bc, int op, int order, double alpha, double dx, int64_t n, int64_t block,
+                     const double *v, double ga, double gb, double *out);
+
 /* Whole-array drivers (line by line along axis `dim`).  g: Dirichlet values, 2 per line
  * (g_a, g_b), NULL = 0.  Return 0 on success, negative on invalid arguments. */
 int sco_local_quad(const sco_grid *g, int dim, int order, double alpha, const double *v,
@@ -64,6 +71,9 @@ int sco_sweep_LR(const sco_grid *g, int dim, double alpha, const double *JL, con
                  double *IL, double *IR, double *ends);
 int sco_apply_invL(const sco_grid *g, int dim, int op, int order, double alpha,
                    const double *gvals, const double *v, double *out);
+/* sco_line_invL_nn along every line of axis `dim`. */
+int sco_apply_invL_nn(const sco_grid *g, int dim, int op, int order, double alpha, int64_t block,
+                      const double *gvals, const double *v, double *out);
 /* out = scale * sum_{p=1..k} D^p[v], D = I - L_op^{-1} (Sec. 2.2, successive relation). */
 int sco_apply_D_partial_sum(const sco_grid *g, int dim, int op, int order, double alpha, int k,
                             double scale, const double *gvals, const double *v, double *out);
