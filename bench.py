@@ -17,11 +17,11 @@ from the committed rocprofv3 counter summaries when they were taken on the curre
 ``cpu_baseline`` times the FP64 oracle on a bounded sample of the same workload on the host cores.
 ``beside`` holds the other workloads measured the same way: the same heat step on the mixed
 FP32/FP64 path, the 2-D advection-diffusion step (4096^2), the 1-D line workload replicated to
-2^18 lines, the ragged batch, the Hamilton-Jacobi solver with classical and learned weights, and a
-plain device copy.
+2^18 lines, the ragged batch, the Hamilton-Jacobi solver with classical and learned weights, a
+plain device copy, and the nearest-neighbour block form of Sec. 3 beside the exact carries.
 
 ``--only LEG`` runs one leg (for profiling): heat3d_f64, heat3d_mixed, advdiff2d, line1d, batch, hj,
-copy.
+copy, nn.
 """
 from __future__ import annotations
 
@@ -227,6 +227,48 @@ def line1d(sc, torch, steps, warmup):
                      "dof_per_s": dof / (m["step_ms_median"] / 1e3),
                      "kernel": m["dominant"], "kernel_mean_ms": m["dominant_mean_ms"],
                      **frac(16 * dof, m["step_ms_median"])}
+    return res
+
+
+def nn_leg(sc, torch, steps, warmup, n=ADV_N):
+    """The nearest-neighbour block form (Sec. 3) beside the exact carries: L_R^{-1} (the advection
+    operator, alpha = beta / (c dt) at dt = dx, beta = 1: nu = 1, so K = ceil(ln(1e16)) = 37 points)
+    along y of a 4096^2 periodic FP64 field, lines cut into 8 virtual blocks of 512 points (one
+    chunk each) that exchange only their block-end integrals.  Timed the same way: the exact
+    single-read launch, the exact aggregate + apply launches, and the block form (aggregate,
+    nearest-neighbour carries, apply)."""
+    from paper_2007_03041_amd import workloads as W
+
+    g = sc.Grid((n, n), (0.0, 0.0), (1.0, 1.0))
+    alpha = float(n)  # nu = alpha dx = 1
+    v = W.fourier_field(n, n, device="cuda")
+    out = torch.empty_like(v)
+    block = sc.chunk_points(g, 1)
+    dof = n * n
+    res = {"workload": f"L_R^{{-1}} along y, {n}x{n} periodic FP64, order 6, nu = 1 (K = 37), "
+                       f"virtual blocks of {block} points",
+           "block_points": block, "window_K": math.ceil(math.log(1e16))}
+    legs = (("exact_single_read", None, None), ("exact_two_launch", None, "0"), ("nn_blocks", block, None))
+    prev = os.environ.get("SC_SINGLE")
+    try:
+        for name, blk, single in legs:
+            if single is None:
+                os.environ.pop("SC_SINGLE", None)
+            else:
+                os.environ["SC_SINGLE"] = single
+            fn = (lambda: sc.apply_invL(v, g, 1, "R", 6, alpha, out=out)) if blk is None else \
+                 (lambda: sc.apply_invL_nn(v, g, 1, "R", 6, alpha, blk, out=out))
+            m = measure(sc, torch, fn, steps, warmup)
+            res[name] = {"ms_min": m["step_ms_min"], "ms_median": m["step_ms_median"],
+                         "kernel_ms": m["kernel_ms"], **frac(16 * dof, m["step_ms_median"])}
+    finally:
+        if prev is None:
+            os.environ.pop("SC_SINGLE", None)
+        else:
+            os.environ["SC_SINGLE"] = prev
+    exact = sc.apply_invL(v, g, 1, "R", 6, alpha)
+    nn = sc.apply_invL_nn(v, g, 1, "R", 6, alpha, block)
+    res["max_rel_diff_nn_vs_exact"] = ((nn - exact).abs().max() / exact.abs().max()).item()
     return res
 
 
@@ -501,7 +543,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no beside legs)")
-    ap.add_argument("--only", choices=("heat3d_f64", "heat3d_mixed", "advdiff2d", "line1d", "batch", "hj", "copy"))
+    ap.add_argument("--only", choices=("heat3d_f64", "heat3d_mixed", "advdiff2d", "line1d", "batch", "hj", "copy",
+                                       "nn"))
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -529,6 +572,8 @@ def main():
             rec = batch_legs(sc, torch)
         elif args.only == "hj":
             rec = hj_legs(sc, torch)
+        elif args.only == "nn":
+            rec = nn_leg(sc, torch, args.steps, args.warmup)
         else:
             rec = copy_leg(torch)
         print(json.dumps({"only": args.only, **rec}), flush=True)
@@ -605,6 +650,8 @@ def main():
         beside["line1d_replicated"] = line1d(sc, torch, args.steps, args.warmup)
         torch.cuda.empty_cache()
         beside["device_copy_1GiB"] = copy_leg(torch)
+        torch.cuda.empty_cache()
+        beside["nn_blocks_4096"] = nn_leg(sc, torch, args.steps, args.warmup)
         torch.cuda.empty_cache()
         beside["batch_4096"] = batch_legs(sc, torch)
         torch.cuda.empty_cache()

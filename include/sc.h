@@ -108,6 +108,28 @@ sc_status sc_apply_invL(const sc_grid *grid, int dim, int op, int order, double 
 sc_status sc_apply_invL_noalloc(const sc_grid *grid, int dim, int op, int order, double alpha,
                                 const double *dirichlet_g, const void *v, void *out, sc_stream_t stream);
 
+/* Points per chunk of the passes along `dim` for this grid (the length of the line segment one
+ * workgroup tile sweeps; lines longer than this are chunked), or -1 for an invalid grid or dim. */
+int64_t sc_chunk_points(const sc_grid *grid, int dim);
+
+/* out = L_op^{-1}[v] along `dim` in the nearest-neighbour block form of Sec. 3: each line is cut
+ * into virtual blocks of block_points points (the last block takes the remainder), the one-GPU
+ * stand-in for the blocks of a domain decomposition.  Each block sweeps its own local integrals
+ * from zero; block i > 0 receives only block i-1's right-moving block-end integral and block
+ * i < last only block i+1's left-moving one (Sec. 3.2/3.3 block operators with the N-N
+ * constants); the line's boundary constants act on the end blocks only: periodic lines take the
+ * periodic choice of Sec. 3.2 (the last block's own I_R at b, the first block's own I_L at a);
+ * Dirichlet lines impose their end values on the end blocks' operators.  The coupling
+ * e^{-alpha (b - a)} between the two ends is dropped.  When every block spans L_m with
+ * e^{-alpha L_m} <= eps (the N-N criterion, eq. (NN constraint general)) the result equals
+ * sc_apply_invL's within eps * max|I| plus rounding; shorter blocks give the truncated operator.
+ * block_points: a positive multiple of sc_chunk_points(grid, dim), or at least the line length
+ * (one block); otherwise SC_ERR_ARG.  Other arguments, layout and the workspace
+ * (sc_workspace_bytes with which = 0) as for sc_apply_invL. */
+sc_status sc_apply_invL_nn(const sc_grid *grid, int dim, int op, int order, double alpha, int64_t block_points,
+                           const double *dirichlet_g, const void *v, void *out, void *ws, size_t ws_bytes,
+                           sc_stream_t stream);
+
 /* out = scale * sum_{p=1..k} D^p[v], D = I - L_op^{-1} (Sec. 2.2, successive relation), k in 1..8.
  * scale = +alpha, -alpha, -alpha^2 gives the left-biased, right-biased and second derivative
  * representations.  Dirichlet axes support k = 1 only (SC_ERR_UNSUPPORTED otherwise). */

@@ -35,7 +35,7 @@ SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_
            "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
            "sc_batch_describe", "sc_hj_workspace_bytes", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
            "sc_mlp_param_count", "sc_mlp_forward", "sc_mlp_grad_workspace_bytes", "sc_mlp_grad", "sc_mlp_adam",
-           "sc_apply_invL_noalloc")
+           "sc_apply_invL_noalloc", "sc_apply_invL_nn", "sc_chunk_points")
 # fixed scratch of sc_apply_invL_noalloc (SC_NOALLOC_SCRATCH_BYTES in include/sc.h)
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -121,6 +121,10 @@ def load():
     lib.sc_apply_invL.argtypes = [gp, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_size_t, c_void_p]
     lib.sc_apply_invL_noalloc.argtypes = [gp, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.sc_apply_invL_nn.argtypes = [gp, c_int, c_int, c_int, c_double, c_int64, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]
+    lib.sc_chunk_points.argtypes = [gp, c_int]
+    lib.sc_chunk_points.restype = c_int64
     lib.sc_apply_D_partial_sum.argtypes = [gp, c_int, c_int, c_int, c_double, c_int, c_double, c_void_p,
                                            c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.sc_time_step.argtypes = [gp, POINTER(sc_linear_pde), c_int, c_void_p, c_void_p, c_size_t, c_void_p]
@@ -162,7 +166,8 @@ def load():
     lib.sc_mlp_grad.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]
     lib.sc_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]
-    for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_invL_noalloc", "sc_apply_D_partial_sum",
+    for f in ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_invL_noalloc", "sc_apply_invL_nn",
+              "sc_apply_D_partial_sum",
               "sc_time_step",
               "sc_timing_enable", "sc_timing_select", "sc_batch_plan_create", "sc_batch_plan_destroy", "sc_batch_apply",
               "sc_batch_apply_per_instance", "sc_batch_tune", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
@@ -287,6 +292,32 @@ def apply_invL_noalloc(v, grid: Grid, dim: int, op: str, order: int, alpha: floa
     gc = grid.c()
     _check(lib.sc_apply_invL_noalloc(ctypes.byref(gc), dim, OPS[op], order, alpha, _gptr(g, grid, dim),
                                      v.data_ptr(), out.data_ptr(), _stream()))
+    return out
+
+
+def chunk_points(grid: Grid, dim: int) -> int:
+    """Points per chunk of the passes along ``dim`` (virtual blocks are multiples of it)."""
+    gc = grid.c()
+    c = int(load().sc_chunk_points(ctypes.byref(gc), dim))
+    if c < 0:
+        raise ScError(SC_ERR_ARG, "invalid grid or dim")
+    return c
+
+
+def apply_invL_nn(v, grid: Grid, dim: int, op: str, order: int, alpha: float, block: int, g=None, out=None):
+    """out = L_op^{-1}[v] along ``dim`` in the nearest-neighbour block form, virtual blocks of ``block``
+    points (a multiple of chunk_points(grid, dim), or at least the line length)."""
+    import torch
+
+    lib = load()
+    _tensor_ok(v, grid, "v")
+    out = torch.empty_like(v) if out is None else out
+    _tensor_ok(out, grid, "out")
+    gc = grid.c()
+    ws, wsp = _workspace(int(lib.sc_workspace_bytes(ctypes.byref(gc), dim, 0, 0)), v.device)
+    nbytes = 0 if ws is None else ws.numel() - 256
+    _check(lib.sc_apply_invL_nn(ctypes.byref(gc), dim, OPS[op], order, alpha, int(block), _gptr(g, grid, dim),
+                                v.data_ptr(), out.data_ptr(), wsp, nbytes, _stream()))
     return out
 
 

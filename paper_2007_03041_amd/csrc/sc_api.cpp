@@ -222,9 +222,11 @@ size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops)
            round256(sizeof(double) * (size_t)(2 * ent + 2 * (int64_t)nops * nlines));
 }
 
+int64_t chunk_points(const Axis &ax, int elem) { return scx::variant(pick_variant(ax.stride == 1, ax.n, elem)).C(); }
+
 int64_t nchunks_for(const Axis &ax, int elem)
 {
-    const int64_t C = scx::variant(pick_variant(ax.stride == 1, ax.n, elem)).C();
+    const int64_t C = chunk_points(ax, elem);
     return (ax.n + C - 1) / C;
 }
 
@@ -257,7 +259,7 @@ int spin_limit()
 // One pass along `dim`: out = acc_term + sum_ops scale * result(op).
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v,
                    const void *acc, int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes,
-                   hipStream_t st)
+                   hipStream_t st, int64_t nn_cpb)
 {
     const Axis ax = axis_of(g, dim);
     const int elem = (int)elem_bytes(g);
@@ -282,7 +284,15 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     for (int o = 0; o < nops; ++o) {
         fill_op(&a.ops[o], ops[o].op, order, ops[o].alpha, ax, vid, ops[o].scale, ops[o].k, ops[o].identity);
         multi = multi || ops[o].k > 1;
+        if (nn_cpb > 0) {
+            // nearest-neighbour blocks: the two ends of the line are more than one block apart
+            // (e^{-alpha (b - a)} below the N-N tolerance), so their coupling is dropped
+            a.ops[o].mu = 0.0;
+            a.ops[o].inv1mmu = 1.0;
+            a.ops[o].dir2inv = 2.0;
+        }
     }
+    if (nn_cpb > 0 && (multi || nn_cpb > INT32_MAX)) return fail(SC_ERR_ARG, "internal: bad nearest-neighbour block");
     if (multi && (nops != 1 || a.nchunks != 1 || ax.bc != SC_BC_PERIODIC || acc_mode != 0))
         return fail(SC_ERR_UNSUPPORTED, "internal: fused powers of D need one periodic operator on whole lines");
     const int64_t tiles = (ax.nlines + scx::variant(vid).TC - 1) / scx::variant(vid).TC;
@@ -314,7 +324,7 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     const int64_t ent = (int64_t)nops * ax.nlines * a.nchunks;
     a.agg = (double *)wsp;
     a.carry = (const double *)(wsp + round256(sizeof(double) * (size_t)(3 * ent)));
-    if (a.nchunks <= kSingleChunks && single_pass_enabled()) {
+    if (a.nchunks <= kSingleChunks && single_pass_enabled() && nn_cpb == 0) {
         // lines of at most 8 chunks: one launch reads the field once; its tiles publish their chunk
         // totals and gather those of the other chunks of their lines (the slots and the claim
         // counter are reset first, by a kernel on the same stream)
@@ -333,7 +343,9 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     }
     // lines of few chunks: every apply tile forms its own carries from the chunk totals (one launch
     // less); longer lines go through the carry launch
-    a.fuse_carry = a.nchunks <= kFuseCarryChunks ? 1 : 0;
+    // (nearest-neighbour blocks always take the carry launch)
+    a.nn_cpb = (int32_t)nn_cpb;
+    a.fuse_carry = (a.nchunks <= kFuseCarryChunks && nn_cpb == 0) ? 1 : 0;
     e = timed(kAgg[dim], st, [&](const char **) {
         return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_AGG, false, st);
     });
@@ -478,6 +490,35 @@ sc_status sc_apply_invL(const sc_grid *grid, int dim, int op, int order, double 
     OpSpec o{(int)op, alpha, 1.0, 0};
     return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes,
                     (hipStream_t)stream);
+}
+
+int64_t sc_chunk_points(const sc_grid *grid, int dim)
+{
+    if (check_grid(grid) != SC_OK || dim < 0 || dim >= grid->ndim) return -1;
+    return chunk_points(axis_of(grid, dim), (int)elem_bytes(grid));
+}
+
+sc_status sc_apply_invL_nn(const sc_grid *grid, int dim, int op, int order, double alpha, int64_t block_points,
+                           const double *dirichlet_g, const void *v, void *out, void *ws, size_t ws_bytes,
+                           sc_stream_t stream)
+{
+    sc_status s = check_line_args(grid, dim, order, alpha);
+    if (s != SC_OK) return s;
+    if (op < SC_OP_L || op > SC_OP_0) return fail(SC_ERR_ARG, "op must be SC_OP_L, SC_OP_R or SC_OP_0");
+    if (!v || !out) return fail(SC_ERR_ARG, "null array pointer");
+    const Axis ax = axis_of(grid, dim);
+    if (overlap(v, out, (size_t)ax.total * elem_bytes(grid))) return fail(SC_ERR_ARG, "out overlaps v");
+    if (ws && ((uintptr_t)ws & 255)) return fail(SC_ERR_ARG, "workspace must be 256-byte aligned");
+    const int64_t C = chunk_points(ax, (int)elem_bytes(grid));
+    if (block_points < 1) return fail(SC_ERR_ARG, "block_points must be positive");
+    if (block_points < ax.n && block_points % C != 0)
+        return fail(SC_ERR_ARG, "block_points must be a multiple of sc_chunk_points (" + std::to_string(C) +
+                                    " on this axis) or at least the line length");
+    const int64_t nch = (ax.n + C - 1) / C;
+    const int64_t cpb = std::min<int64_t>(block_points >= ax.n ? nch : block_points / C, nch);
+    OpSpec o{(int)op, alpha, 1.0, 0};
+    return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes,
+                    (hipStream_t)stream, cpb);
 }
 
 sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order, double alpha, int k,

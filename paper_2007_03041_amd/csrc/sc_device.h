@@ -64,7 +64,8 @@ struct PassArgs {
     int32_t fuse_carry;     // chunked apply: each tile forms its chunk carries from the aggregates
     uint32_t *sync;         // single-pass chunked launches: the tile claim counter
     int32_t spin_limit;     // single-pass: polls of the other chunks' totals before a tile gives up
-    int32_t pad_;
+    int32_t nn_cpb;         // > 0: nearest-neighbour virtual blocks of this many chunks (carry launch
+                            // and apply); 0: exact carries over the whole line
     // Dirichlet ends: the one-sided stencils of the order/2 points nearest an end integrate the
     // interpolant through the `order` end values; extending the line by that interpolant's values
     // at m = 1..order/2 points beyond the end makes the centred interior stencil integrate the same

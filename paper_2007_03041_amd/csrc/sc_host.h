@@ -89,8 +89,11 @@ void fill_op(OpArgs *P, int op, int order, double alpha, const Axis &ax, int vid
 void fill_ext(PassArgs *a, int order);
 size_t chunk_ws_bytes(int64_t nlines, int64_t nchunks, int nops);
 int64_t nchunks_for(const Axis &ax, int elem);
+// nn_cpb > 0: nearest-neighbour virtual blocks of nn_cpb chunks (the line's mu terms dropped)
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v, const void *acc,
-                   int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes, hipStream_t st);
+                   int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes, hipStream_t st,
+                   int64_t nn_cpb = 0);
+int64_t chunk_points(const Axis &ax, int elem);
 sc_status check_line_args(const sc_grid *g, int dim, int order, double alpha);
 
 }  // namespace host

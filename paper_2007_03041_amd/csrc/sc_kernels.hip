@@ -26,6 +26,45 @@ extern template int line_pass_batch_occupancy_t<double, 6>(int, int);
 extern template int line_pass_batch_occupancy_t<float, 4>(int, int);
 extern template int line_pass_batch_occupancy_t<float, 6>(int, int);
 
+// Nearest-neighbour carries (Sec. 3.2/3.3 block operators under the N-N criterion): the line is cut
+// into virtual blocks of cpb chunks.  Within a block the chunks chain exactly; the first chunk of
+// block b > 0 receives block b-1's own total (its sweep from zero), the last chunk of block b < last
+// receives block b+1's own total, and nothing comes from further away.  Periodic lines take the
+// periodic choice for the wrap (the last block's own I_R at b, the first block's own I_L at a);
+// Dirichlet lines impose their end values on the end blocks' operators, whose end integrals are
+// the carried sweeps at the end points.  The operator's mu terms are zero here (set on the host).
+__device__ void chunk_carry_nn(const PassArgs &a, const OpArgs &P, const double *ag, double *cr, double ga,
+                               double gb, double &Ap, double &Bp)
+{
+    const int64_t nch = a.nchunks, cpb = a.nn_cpb;
+    double E = 0.0, T = 0.0;  // carried sweep, and the current block's own sweep
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        if (ch % cpb == 0) {
+            E = T;  // the previous block's own total (zero before block 0)
+            T = 0.0;
+        }
+        cr[2 * ch + 0] = E;
+        const double dc = ch == nch - 1 ? P.dchunk_last : P.dchunk;
+        E = fma(dc, E, ag[3 * ch + 0]);
+        T = fma(dc, T, ag[3 * ch + 0]);
+    }
+    double F = 0.0, U = 0.0;
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+        if (ch == nch - 1 || (ch + 1) % cpb == 0) {
+            F = U;  // the next block's own total (zero after the last block)
+            U = 0.0;
+        }
+        cr[2 * ch + 1] = F;
+        const double dc = ch == nch - 1 ? P.dchunk_last : P.dchunk;
+        F = fma(dc, F, ag[3 * ch + 1]);
+        U = fma(dc, U, ag[3 * ch + 1]);
+    }
+    if (a.bc == 0)
+        boundary_constants(P, 0, T, U, ag[2], 0.0, 0.0, Ap, Bp);
+    else
+        boundary_constants(P, 1, E, F, ag[2], ga, gb, Ap, Bp);
+}
+
 // Chunk carries of chunked passes: one thread per (op, line) walks the chunk totals in both
 // directions (Sec. 3, eqs. (Left-/Right-moving integral DD) with exact attenuation factors) and
 // forms the boundary constants.
@@ -37,6 +76,16 @@ __device__ void chunk_carry_one(const PassArgs &a, const double *agg, double *ca
     const int64_t nch = a.nchunks;
     const double *ag = agg + ((int64_t)o * a.nlines + L) * nch * 3;
     double *cr = carry + ((int64_t)o * a.nlines + L) * nch * 2;
+    if (a.nn_cpb > 0) {
+        const double ga = (a.bc == 1 && g) ? g[2 * L + 0] : 0.0;
+        const double gb = (a.bc == 1 && g) ? g[2 * L + 1] : 0.0;
+        double Ap = 0.0, Bp = 0.0;
+        chunk_carry_nn(a, P, ag, cr, ga, gb, Ap, Bp);
+        double *ab = carry + 2 * (int64_t)a.nops * a.nlines * nch + 2 * idx;
+        ab[0] = Ap;
+        ab[1] = Bp;
+        return;
+    }
     double E = 0.0;
     for (int64_t ch = 0; ch < nch; ++ch) {
         cr[2 * ch + 0] = E;

@@ -158,3 +158,27 @@ def test_lines_beyond_32_bit_tile_indexing_are_refused():
     h = ctypes.c_void_p()
     assert lib.sc_batch_plan_create(arr, 1, sc.SC_F64, 6, ctypes.byref(h)) == sc.SC_ERR_SHAPE
     assert not h.value
+
+
+def test_nearest_neighbour_entry_point_validation():
+    """sc_chunk_points reports the chunk length per axis (contiguous x: 8192 points for long lines;
+    strided FP64: 512 up to 8192 points); sc_apply_invL_nn validates like sc_apply_invL and
+    refuses virtual blocks that are not whole chunks, before anything is enqueued."""
+    lib = sc.load()
+    g = sc.Grid((20000, 4096))
+    gc = g.c()
+    assert sc.chunk_points(g, 0) == 8192
+    assert sc.chunk_points(g, 1) == 512
+    assert lib.sc_chunk_points(ctypes.byref(gc), 2) == -1
+    call = lambda dim, block, op=1, order=6, alpha=100.0: lib.sc_apply_invL_nn(
+        ctypes.byref(gc), dim, op, order, alpha, block, None, 0x1000, 0x1000 + 8 * 20000 * 4096, None, 0, None)
+    assert call(1, 700) == sc.SC_ERR_ARG
+    assert "multiple" in lib.sc_last_error().decode()
+    assert call(1, 0) == sc.SC_ERR_ARG
+    assert call(1, -512) == sc.SC_ERR_ARG
+    assert call(1, 512, op=3) == sc.SC_ERR_ARG
+    assert call(1, 512, order=5) == sc.SC_ERR_UNSUPPORTED
+    assert call(1, 512, alpha=0.0) == sc.SC_ERR_ARG
+    # whole-chunk blocks pass validation (then fail on the missing workspace)
+    assert call(1, 1024) == sc.SC_ERR_WORKSPACE
+    assert call(0, 8192) == sc.SC_ERR_WORKSPACE
