@@ -248,7 +248,7 @@ def nn_leg(sc, torch, steps, warmup, n=ADV_N):
     res = {"workload": f"L_R^{{-1}} along y, {n}x{n} periodic FP64, order 6, nu = 1 (K = 37), "
                        f"virtual blocks of {block} points",
            "block_points": block, "window_K": math.ceil(math.log(1e16))}
-    legs = (("exact_single_read", None, None), ("exact_two_launch", None, "0"), ("nn_blocks", block, None))
+    legs = (("exact_single_read", None, "1"), ("exact_two_launch", None, None), ("nn_blocks", block, None))
     prev = os.environ.get("SC_SINGLE")
     try:
         for name, blk, single in legs:

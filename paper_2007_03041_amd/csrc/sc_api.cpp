@@ -235,11 +235,15 @@ constexpr int64_t kFuseCarryChunks = 16;
 // ... and with at most this many run as one single-pass launch (the gathered totals sit in registers)
 constexpr int64_t kSingleChunks = 8;
 
-// SC_SINGLE=0 selects the two-launch form (aggregate, then apply) for every chunked pass
+// SC_SINGLE=1 selects the single-read form for chunked passes of at most kSingleChunks chunks.  It
+// is not the default: at 4096^2 FP64 its y pass measured slower than the aggregate + apply launches
+// (one operator 0.095 vs 0.089 ms; the advection-diffusion pair 0.097 vs 0.096 ms), because a tile's
+// wait for its line's other chunk totals (published and polled at device scope, across the chips'
+// separate L2 caches) costs more than the second read of the field.
 bool single_pass_enabled()
 {
     const char *env = std::getenv("SC_SINGLE");
-    return !(env && env[0] == '0');
+    return env && env[0] == '1';
 }
 
 // polls of the other chunks' totals before a single-pass tile gives up and writes NaN (SC_SPIN_LIMIT;

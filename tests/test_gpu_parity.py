@@ -544,8 +544,8 @@ SINGLE_CASES = [
 
 @pytest.mark.parametrize("n,dim,bc,order", SINGLE_CASES)
 def test_single_pass_chunked_lines(gpu_lib, n, dim, bc, order, monkeypatch):
-    """Lines of 2..8 chunks in one launch (each tile publishes its chunk totals and gathers the
-    others'): against the oracle, and bit for bit against the aggregate + apply launches."""
+    """Lines of 2..8 chunks in one launch (SC_SINGLE=1: each tile publishes its chunk totals and
+    gathers the others'): against the oracle, and bit for bit against the aggregate + apply launches."""
     sc = gpu_lib
     v = W.random_field(tuple(reversed(n)), index=71 + dim)
     g = Grid(n, tuple(0.0 for _ in n), tuple(1.0 + e for e in range(len(n))), tuple(bc for _ in n))
@@ -554,11 +554,11 @@ def test_single_pass_chunked_lines(gpu_lib, n, dim, bc, order, monkeypatch):
     for op, nu in (("0", 0.03), ("R", 1.0), ("L", 0.2)):
         alpha = nu / g.dx(dim)
         ref = oracle.apply_invL(ogrid(g), dim, op, order, alpha, v, gv)
+        monkeypatch.setenv("SC_SINGLE", "1")
         got = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv))).copy()
-        assert err(got, ref, np.abs(ref).max()) < TOL, op
-        monkeypatch.setenv("SC_SINGLE", "0")
-        two = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv)))
         monkeypatch.delenv("SC_SINGLE")
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+        two = host(sc.apply_invL(dev(v), g, dim, op, order, alpha, g=None if gv is None else dev(gv)))
         assert np.array_equal(got, two), op
 
 
@@ -570,6 +570,7 @@ def test_single_pass_bounded_wait_gives_up_with_nan(gpu_lib, monkeypatch):
     n = (128, 4096)
     v = W.random_field((n[1], n[0]), index=72)
     g = Grid(n)
+    monkeypatch.setenv("SC_SINGLE", "1")
     monkeypatch.setenv("SC_SPIN_LIMIT", "-3")
     out = host(sc.apply_invL(dev(v), g, 1, "0", 4, 40.0))
     assert np.isnan(out).all()
