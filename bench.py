@@ -536,6 +536,73 @@ def cpu_baseline(sc, torch, reps=10, warm=3):
     }
 
 
+# ------------------------------------------------------------------------------------------------
+# counter ingestion: rocprofv3 --pmc summaries -> profiles/traffic_counters.json
+# ------------------------------------------------------------------------------------------------
+PASS_ORDER = {"heat3d_f64": ("line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z"),
+              "heat3d_mixed": ("line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z")}
+
+
+def _counter_means(path, counter, filt):
+    """Per-dispatch values of one counter, in dispatch order, for kernels whose name contains filt."""
+    import csv
+
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and filt in r["Kernel_Name"]:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def ingest_counters(specs, copy_dir):
+    """specs: WORKLOAD=DIR pairs, DIR holding fetch/ and write/ rocprofv3 --pmc runs of
+    `bench.py --only WORKLOAD`; copy_dir: fetch/ and write/ runs of `bench.py --calibrate-copy`.
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what each reads per byte of a 1 GiB
+    device copy; the library's passes of a step are launched in PASS_ORDER, which names them."""
+    def per_byte(counter, sub):
+        rows = _counter_means(os.path.join(copy_dir, sub, "run_counter_collection.csv"), counter, "")
+        big = [v for _, k, v in rows if "copy" in k.lower() or "elementwise" in k.lower()]
+        kib = max(big)  # the 1 GiB copy dispatch: its fetch covers the source, its write the destination
+        return kib * 1024.0 / float(1 << 30)
+
+    sf, sw = per_byte("FETCH_SIZE", "cfetch"), per_byte("WRITE_SIZE", "cwrite")
+    rec = {"kernel_source_sha": kernel_source_sha(), "copy_scale_fetch": sf, "copy_scale_write": sw,
+           "note": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) divided by what each counter reads per byte "
+                   "moved by a 1 GiB device copy, averaged over every dispatch of the pass",
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/cfetch -o run -- python3 bench.py "
+                        "--calibrate-copy",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/cwrite -o run -- python3 bench.py "
+                        "--calibrate-copy"],
+           "workloads": {}}
+    for spec in specs:
+        wl, d = spec.split("=", 1)
+        names = PASS_ORDER[wl]
+        out = {}
+        for counter, sub, scale, key in (("FETCH_SIZE", "fetch", sf, "fetch_bytes_per_launch"),
+                                         ("WRITE_SIZE", "write", sw, "write_bytes_per_launch")):
+            rows = _counter_means(os.path.join(d, sub, "run_counter_collection.csv"), counter, "scx::")
+            acc = {}
+            for i, (_, kname, v) in enumerate(rows):
+                nm = names[i % len(names)]
+                e = acc.setdefault(nm, {"rocprof_name": kname, "vals": []})
+                e["vals"].append(v * 1024.0 / scale)
+            for nm, e in acc.items():
+                o = out.setdefault(nm, {"rocprof_name": e["rocprof_name"], "dispatches": len(e["vals"])})
+                o[key] = sum(e["vals"]) / len(e["vals"])
+        for o in out.values():
+            o["hbm_bytes_per_launch"] = o.get("fetch_bytes_per_launch", 0.0) + o.get("write_bytes_per_launch", 0.0)
+        rec["workloads"][wl] = out
+        for sub, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+            rec["commands"].append(f"rocprofv3 --pmc {counter} --output-format csv -d DIR/{sub} -o run -- python3 "
+                                   f"bench.py --only {wl} --steps 2 --warmup 1")
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -546,7 +613,13 @@ def main():
     ap.add_argument("--only", choices=("heat3d_f64", "heat3d_mixed", "advdiff2d", "line1d", "batch", "hj", "copy",
                                        "nn"))
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="WORKLOAD=DIR",
+                    help="write profiles/traffic_counters.json from rocprofv3 --pmc runs (no GPU needed)")
+    ap.add_argument("--copy-dir", help="with --ingest-counters: the copy calibration runs")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(args.ingest_counters, args.copy_dir), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
