@@ -235,6 +235,27 @@ constexpr int64_t kFuseCarryChunks = 16;
 // ... and with at most this many run as one single-pass launch (the gathered totals sit in registers)
 constexpr int64_t kSingleChunks = 8;
 
+// Windowed chunk carries (chunked contiguous one-line tiles of one operator): the carries into a
+// chunk are the sweeps over the K points on either side of it, K = ceil(60 ln 2 / nu), so that the
+// dropped remainder is below 2^-60 of the carry.  Used where K <= 128 and the first and last chunks
+// are longer than K plus the stencil (the end constants then act on their own chunks only, and
+// Dirichlet windows stay inside the line).  Returns K, or 0 where the exact carries are taken.
+// SC_WINDOW=0 always takes the exact carries.
+int window_k(const scx::PassArgs &a, int order, const scx::Variant &V, bool multi)
+{
+    const char *env = std::getenv("SC_WINDOW");
+    if (env && env[0] == '0') return 0;
+    if (!V.contig || V.TC != 1 || a.nops != 1 || multi || a.nchunks < 2 || a.stride != 1) return 0;
+    const double nu = a.ops[0].nu;
+    const double kd = std::ceil(60.0 * std::log(2.0) / nu);
+    if (!(kd <= 128.0)) return 0;
+    const int64_t K = (int64_t)kd;
+    const int64_t C = V.C();
+    const int64_t last = a.n - (a.nchunks - 1) * C;
+    if (C < K + order + 1 || last < K + order + 1) return 0;
+    return (int)K;
+}
+
 // SC_SINGLE=1 selects the single-read form for chunked passes of at most kSingleChunks chunks.  It
 // is not the default: at 4096^2 FP64 its y pass measured slower than the aggregate + apply launches
 // (one operator 0.095 vs 0.089 ms; the advection-diffusion pair 0.097 vs 0.096 ms), because a tile's
@@ -322,6 +343,22 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
         });
         if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         return SC_OK;
+    }
+    if (nn_cpb == 0) {
+        const int K = window_k(a, order, scx::variant(vid), multi);
+        if (K > 0) {
+            // windowed carries: one launch, no workspace; the two ends' coupling (below 2^-60 here,
+            // since the line is longer than K) is dropped
+            a.win_k = K;
+            a.ops[0].mu = 0.0;
+            a.ops[0].inv1mmu = 1.0;
+            a.ops[0].dir2inv = 2.0;
+            e = timed(kApply[dim], st, [&](const char **) {
+                return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_APPLY, false, st);
+            });
+            if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+            return SC_OK;
+        }
     }
     const size_t need = chunk_ws_bytes(ax.nlines, a.nchunks, nops);
     if (!wsp || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small for a chunked pass");

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -64,6 +65,16 @@ ClassKey class_of(const sc_batch_item &it, int elem, int order)
 Choice default_choice(const sc_batch_item &it, int elem)
 {
     Choice c;
+    // SC_BATCH_VARIANT=<variant>[p]: every untuned instance takes that x-line variant (p: persistent)
+    if (const char *env = std::getenv("SC_BATCH_VARIANT")) {
+        const int vid = std::atoi(env);
+        for (int v : kBatchVariants)
+            if (v == vid && variant_built(vid, elem)) {
+                c.vid = vid;
+                c.persistent = std::strchr(env, 'p') ? 1 : 0;
+                return c;
+            }
+    }
     if (it.nlines >= 4) {
         c.vid = it.n <= 256 ? 0 : it.n <= 512 ? 10 : it.n <= 1024 ? 1 : it.n <= 2048 ? 16 : it.n <= 4096 ? 2 : 3;
     } else {
@@ -98,6 +109,7 @@ size_t item_chunk_doubles(const sc_batch_item &it, int64_t C)
 struct Launch {
     int kind = 0;  // 0: line pass, 1: chunk carry
     int vid = 0, mode = 0;
+    int full = 0;  // line pass over tiles that end inside their line (the lean instantiation)
     int64_t nwork = 0, grid = 0;
     size_t off = 0;  // byte offset of the work list / item list in the device buffer
 };
@@ -137,7 +149,8 @@ sc_status build(sc_batch_plan p)
 {
     const int count = (int)p->items.size();
     std::vector<BatchArgs> table(count);
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;  // (vid, persistent, chunked) -> items
+    // (vid, persistent, chunked: 0 whole lines, 1 exact chunk carries, 2 windowed carries) -> items
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
     size_t wsd = 0;
     for (int i = 0; i < count; ++i) {
         const sc_batch_item &it = p->items[i];
@@ -160,22 +173,33 @@ sc_status build(sc_batch_plan p)
         b.v_off = it.offset;
         b.g_off = it.g_offset;
         b.agg_off = b.carry_off = 0;
-        if (a.nchunks > 1) {
-            const int64_t ent = it.nlines * a.nchunks;
-            b.agg_off = (int64_t)wsd;
-            b.carry_off = (int64_t)wsd + 3 * ent;
-            wsd += item_chunk_doubles(it, V.C());
+        int chunked = a.nchunks > 1 ? 1 : 0;
+        if (chunked) {
+            const int K = window_k(a, p->order, V, false);
+            if (K > 0) {
+                // windowed carries: the apply launch alone, no workspace
+                a.win_k = K;
+                a.ops[0].mu = 0.0;
+                a.ops[0].inv1mmu = 1.0;
+                a.ops[0].dir2inv = 2.0;
+                chunked = 2;
+            } else {
+                const int64_t ent = it.nlines * a.nchunks;
+                b.agg_off = (int64_t)wsd;
+                b.carry_off = (int64_t)wsd + 3 * ent;
+                wsd += item_chunk_doubles(it, V.C());
+            }
         }
-        groups[std::make_tuple(ch.vid, ch.persistent, a.nchunks > 1 ? 1 : 0)].push_back(i);
+        groups[std::make_tuple(ch.vid, ch.persistent, chunked)].push_back(i);
     }
     // work lists, in launch order: every fused group, then the chunked groups' phases
     std::vector<char> host(round256(sizeof(BatchArgs) * (size_t)count));
     std::memcpy(host.data(), table.data(), sizeof(BatchArgs) * (size_t)count);
     std::vector<Launch> launches;
-    auto occ_grid = [&](int vid, int mode, int pers, int64_t nwork) {
+    auto occ_grid = [&](int vid, int mode, int full, int pers, int64_t nwork) {
         int64_t grid = nwork;
         if (pers) {
-            const int occ = std::max(1, line_pass_batch_occupancy(p->elem, p->order, vid, mode));
+            const int occ = std::max(1, line_pass_batch_occupancy(p->elem, p->order, vid, mode, full));
             grid = std::min<int64_t>(nwork, (int64_t)occ * p->num_cu);
         }
         return std::max<int64_t>(1, std::min<int64_t>(grid, INT32_MAX));
@@ -190,6 +214,7 @@ sc_status build(sc_batch_plan p)
         for (auto &kv : groups) {
             const int vid = std::get<0>(kv.first), pers = std::get<1>(kv.first), chunked = std::get<2>(kv.first);
             if ((phase == 0) != (chunked == 0)) continue;
+            if (chunked == 2 && phase != 3) continue;  // windowed: the apply launch only
             const Variant &V = variant(vid);
             Launch L;
             L.vid = vid;
@@ -204,17 +229,28 @@ sc_status build(sc_batch_plan p)
                 launches.push_back(L);
                 continue;
             }
-            std::vector<BatchWork> w;
+            // tiles that end inside their line (every chunk but a ragged last one) run the lean
+            // instantiation without the per-point end rules; the others the general one
+            std::vector<BatchWork> w[2];
             for (int i : kv.second) {
                 const BatchArgs &b = table[i];
                 const int64_t tiles = (b.a.nlines + V.TC - 1) / V.TC;
-                for (int64_t t = 0; t < tiles * b.a.nchunks; ++t) w.push_back(BatchWork{i, 0, t});
+                // (windowed items take a ragged last chunk as the full tile ending at the line's end)
+                const bool ragged = b.a.n % V.C() != 0 && b.a.win_k == 0;
+                for (int64_t t = 0; t < tiles * b.a.nchunks; ++t) {
+                    const bool last = t % b.a.nchunks == b.a.nchunks - 1;
+                    w[(ragged && last) ? 0 : 1].push_back(BatchWork{i, 0, t});
+                }
             }
             L.mode = phase == 0 ? LMODE_FUSED : phase == 1 ? LMODE_AGG : LMODE_APPLY;
-            L.nwork = (int64_t)w.size();
-            L.grid = occ_grid(vid, L.mode, pers, L.nwork);
-            L.off = add_work(w);
-            launches.push_back(L);
+            for (int full = 1; full >= 0; --full) {
+                if (w[full].empty()) continue;
+                L.full = full;
+                L.nwork = (int64_t)w[full].size();
+                L.grid = occ_grid(vid, L.mode, full, pers, L.nwork);
+                L.off = add_work(w[full]);
+                launches.push_back(L);
+            }
         }
     }
     drop_graph(p);
@@ -243,13 +279,17 @@ hipError_t enqueue(sc_batch_plan p, const void *v, void *out, const double *g, v
             if (L.kind == 1)
                 return launch_chunk_carry_batch(table, (const int32_t *)(p->dev + L.off), (int)L.nwork, g,
                                                 (double *)ws, st);
-            BatchLaunch b{table, (const BatchWork *)(p->dev + L.off), L.nwork, L.grid, v, out, g, (double *)ws, L.mode};
+            BatchLaunch b{table, (const BatchWork *)(p->dev + L.off), L.nwork, L.grid, v, out, g, (double *)ws, L.mode,
+                          L.full};
             return launch_line_pass_batch(b, p->elem, p->order, L.vid, st);
         };
         if (time_it) {
-            const char *nm = L.kind == 1 ? "batch_chunk_carry"
+            // timing names carry the launch's shape: batch_<phase>_v<variant><p: persistent, o: one
+            // workgroup per item>[f: tiles that end inside their line]
+            std::string nm = L.kind == 1 ? "batch_chunk_carry"
                                          : L.mode == LMODE_FUSED ? "batch_fused" : L.mode == LMODE_AGG ? "batch_agg" : "batch_apply";
-            e = timed(nm, st, run);
+            if (L.kind == 0) nm += "_v" + std::to_string(L.vid) + (L.grid < L.nwork ? "p" : "o") + (L.full ? "f" : "");
+            e = timed(nm.c_str(), st, run);
         } else {
             e = run(nullptr);
         }

@@ -66,6 +66,9 @@ struct PassArgs {
     int32_t spin_limit;     // single-pass: polls of the other chunks' totals before a tile gives up
     int32_t nn_cpb;         // > 0: nearest-neighbour virtual blocks of this many chunks (carry launch
                             // and apply); 0: exact carries over the whole line
+    int32_t win_k;          // > 0: windowed apply of chunked one-line tiles: the carries are the
+                            // sweeps over the win_k points before and after the chunk
+    int32_t pad_;
     // Dirichlet ends: the one-sided stencils of the order/2 points nearest an end integrate the
     // interpolant through the `order` end values; extending the line by that interpolant's values
     // at m = 1..order/2 points beyond the end makes the centred interior stencil integrate the same

@@ -94,6 +94,8 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
                    int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes, hipStream_t st,
                    int64_t nn_cpb = 0);
 int64_t chunk_points(const Axis &ax, int elem);
+// K of the windowed chunk carries for this pass and tile shape, or 0 (exact carries)
+int window_k(const PassArgs &a, int order, const Variant &V, bool multi);
 sc_status check_line_args(const sc_grid *g, int dim, int order, double alpha);
 
 }  // namespace host

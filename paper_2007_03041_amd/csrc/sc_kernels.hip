@@ -17,14 +17,22 @@ extern template hipError_t launch_line_pass_pipe_t<double, 4>(const PassArgs &, 
 extern template hipError_t launch_line_pass_pipe_t<double, 6>(const PassArgs &, int, hipStream_t);
 extern template hipError_t launch_line_pass_pipe_t<float, 4>(const PassArgs &, int, hipStream_t);
 extern template hipError_t launch_line_pass_pipe_t<float, 6>(const PassArgs &, int, hipStream_t);
-extern template hipError_t launch_line_pass_batch_t<double, 4>(const BatchLaunch &, int, hipStream_t);
-extern template hipError_t launch_line_pass_batch_t<double, 6>(const BatchLaunch &, int, hipStream_t);
-extern template hipError_t launch_line_pass_batch_t<float, 4>(const BatchLaunch &, int, hipStream_t);
-extern template hipError_t launch_line_pass_batch_t<float, 6>(const BatchLaunch &, int, hipStream_t);
-extern template int line_pass_batch_occupancy_t<double, 4>(int, int);
-extern template int line_pass_batch_occupancy_t<double, 6>(int, int);
-extern template int line_pass_batch_occupancy_t<float, 4>(int, int);
-extern template int line_pass_batch_occupancy_t<float, 6>(int, int);
+extern template hipError_t launch_line_pass_batch_t<double, 4, false>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<double, 4, true>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<double, 6, false>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<double, 6, true>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 4, false>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 4, true>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 6, false>(const BatchLaunch &, int, hipStream_t);
+extern template hipError_t launch_line_pass_batch_t<float, 6, true>(const BatchLaunch &, int, hipStream_t);
+extern template int line_pass_batch_occupancy_t<double, 4, false>(int, int);
+extern template int line_pass_batch_occupancy_t<double, 4, true>(int, int);
+extern template int line_pass_batch_occupancy_t<double, 6, false>(int, int);
+extern template int line_pass_batch_occupancy_t<double, 6, true>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 4, false>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 4, true>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 6, false>(int, int);
+extern template int line_pass_batch_occupancy_t<float, 6, true>(int, int);
 
 // Nearest-neighbour carries (Sec. 3.2/3.3 block operators under the N-N criterion): the line is cut
 // into virtual blocks of cpb chunks.  Within a block the chunks chain exactly; the first chunk of
@@ -252,8 +260,11 @@ hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int
 {
     if (!variant_built(vid, elem)) return hipErrorInvalidValue;
     // lines that are a whole number of chunks have no segment past their end: the kernels without
-    // the per-point end rules keep fewer registers live and reach a higher occupancy
-    const bool full = a.n % variant(vid).C() == 0;
+    // the per-point end rules keep fewer registers live and reach a higher occupancy.  Windowed
+    // applies take a ragged last chunk as the full tile ending at the line's end, so all their tiles
+    // are full.
+    const bool full = a.n % variant(vid).C() == 0 || (a.win_k > 0 && mode == LMODE_APPLY && variant(vid).contig &&
+                                                      variant(vid).TC == 1 && a.n >= variant(vid).C());
     if (elem == 8) {
         if (order == 4)
             return full ? launch_line_pass_t<double, 4, true>(a, vid, mode, multi, st)
@@ -303,19 +314,34 @@ hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int
     if (!variant_built(vid, elem) || !variant(vid).contig) return hipErrorInvalidValue;
     if (b.nwork <= 0) return hipSuccess;
     if (elem == 8) {
-        if (order == 4) return launch_line_pass_batch_t<double, 4>(b, vid, st);
-        return launch_line_pass_batch_t<double, 6>(b, vid, st);
+        if (order == 4)
+            return b.full ? launch_line_pass_batch_t<double, 4, true>(b, vid, st)
+                          : launch_line_pass_batch_t<double, 4, false>(b, vid, st);
+        return b.full ? launch_line_pass_batch_t<double, 6, true>(b, vid, st)
+                      : launch_line_pass_batch_t<double, 6, false>(b, vid, st);
     }
-    if (order == 4) return launch_line_pass_batch_t<float, 4>(b, vid, st);
-    return launch_line_pass_batch_t<float, 6>(b, vid, st);
+    if (order == 4)
+        return b.full ? launch_line_pass_batch_t<float, 4, true>(b, vid, st)
+                      : launch_line_pass_batch_t<float, 4, false>(b, vid, st);
+    return b.full ? launch_line_pass_batch_t<float, 6, true>(b, vid, st)
+                  : launch_line_pass_batch_t<float, 6, false>(b, vid, st);
 }
 
-int line_pass_batch_occupancy(int elem, int order, int vid, int mode)
+int line_pass_batch_occupancy(int elem, int order, int vid, int mode, int full)
 {
     if (!variant_built(vid, elem) || !variant(vid).contig) return 0;
-    if (elem == 8) return order == 4 ? line_pass_batch_occupancy_t<double, 4>(vid, mode)
-                                     : line_pass_batch_occupancy_t<double, 6>(vid, mode);
-    return order == 4 ? line_pass_batch_occupancy_t<float, 4>(vid, mode) : line_pass_batch_occupancy_t<float, 6>(vid, mode);
+    if (elem == 8) {
+        if (order == 4)
+            return full ? line_pass_batch_occupancy_t<double, 4, true>(vid, mode)
+                        : line_pass_batch_occupancy_t<double, 4, false>(vid, mode);
+        return full ? line_pass_batch_occupancy_t<double, 6, true>(vid, mode)
+                    : line_pass_batch_occupancy_t<double, 6, false>(vid, mode);
+    }
+    if (order == 4)
+        return full ? line_pass_batch_occupancy_t<float, 4, true>(vid, mode)
+                    : line_pass_batch_occupancy_t<float, 4, false>(vid, mode);
+    return full ? line_pass_batch_occupancy_t<float, 6, true>(vid, mode)
+                : line_pass_batch_occupancy_t<float, 6, false>(vid, mode);
 }
 
 hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems,

@@ -41,11 +41,12 @@ struct BatchLaunch {
     const double *g;
     double *ws;
     int mode;                // LMODE_*
+    int full;                // every work item's tile ends inside its line (no per-point end rules)
 };
 
 hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st);
 // resident workgroups per CU of the batched pass (0 if the variant is not built for x lines)
-int line_pass_batch_occupancy(int elem, int order, int vid, int mode);
+int line_pass_batch_occupancy(int elem, int order, int vid, int mode, int full);
 hipError_t launch_chunk_carry_batch(const BatchArgs *table, const int32_t *items, int nitems,
                                     const double *g, double *ws, hipStream_t st);
 
@@ -54,9 +55,9 @@ template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_t(const PassArgs &a, int vid, int mode, bool multi, hipStream_t st);
 template <typename T, int ORDER>
 hipError_t launch_line_pass_pipe_t(const PassArgs &a, int vid, hipStream_t st);
-template <typename T, int ORDER>
+template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_batch_t(const BatchLaunch &b, int vid, hipStream_t st);
-template <typename T, int ORDER>
+template <typename T, int ORDER, bool FULL>
 int line_pass_batch_occupancy_t(int vid, int mode);
 
 double moment(int q, double nu);

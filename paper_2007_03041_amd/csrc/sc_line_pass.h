@@ -297,6 +297,22 @@ __device__ __forceinline__ double decayed(double A, double nu, int64_t m)
     return x > 745.0 ? 0.0 : A * exp(-x);
 }
 
+// d^m for 0 <= m < 128 by binary powers of the operator's decay table (no exp on the device)
+template <class OA>
+__device__ __forceinline__ double dpow_small(const OA &P, int m)
+{
+    static_assert(MAXS >= 16, "decay table reaches d^16");
+    const double d16 = P.dpow[16], d32 = d16 * d16, d64 = d32 * d32;
+    double r = (m & 1) ? P.dpow[1] : 1.0;
+    if (m & 2) r *= P.dpow[2];
+    if (m & 4) r *= P.dpow[4];
+    if (m & 8) r *= P.dpow[8];
+    if (m & 16) r *= d16;
+    if (m & 32) r *= d32;
+    if (m & 64) r *= d64;
+    return r;
+}
+
 // Boundary constants A', B' of one line from its sweep totals: I_R at the last point (IRn), I_L at
 // the first point (IL0) and J_R at x_0 (J0).  Periodic lines (Sec. 2.3): A' = (d IRn + J0)/(1 - mu),
 // B' = IL0/(1 - mu).  Dirichlet lines: the end values ga, gb fix them; for L_0 through the 2x2
@@ -689,15 +705,17 @@ line_pass_pipe(const PassArgs a_arg, int64_t ntiles)
 // Persistent pass over a batch of independent instances: workgroup b takes work items b, b + grid,
 // ... of the list; each item is one tile of one instance, whose argument block (coefficients, sizes,
 // element offsets of its arrays) lives in a device table.  Items of one launch share the tile shape.
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
+// FULL: every item's tile ends inside its line.  Register budgets as measured on the ragged batch:
+// 168 VGPRs (3 waves per SIMD) for general tiles and for FP64 applies, whose 128-register form
+// spills (3.43 vs 3.06 ms); 128 for the rest (FP32 applies 2.29 vs 2.59 ms).
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, bool FULL>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FULL && (MODE != MODE_APPLY || sizeof(T) == 4)) ? 4 : 3)))
 line_pass_batch(const BatchArgs *__restrict__ table,
                                                      const BatchWork *__restrict__ work, int64_t nwork,
                                                      const T *vbase, T *obase, const double *gbase, double *wsbase)
 {
     constexpr int NOPS = 1;
     constexpr bool MULTI = false;
-    constexpr bool FULL = false;
     constexpr bool PIPE = false;
     constexpr bool pipe_first = false;
     constexpr int64_t pipe_next = -1;
@@ -762,7 +780,8 @@ static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStrea
 template <typename T, int ORDER, bool FULL, int S, int TC, bool CONTIG, int NT>
 static hipError_t launch_variant(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
-    if (FULL && a.n % ((NT / TC) * S) != 0) return hipErrorInvalidValue;
+    if (FULL && a.n % ((NT / TC) * S) != 0 && !(a.win_k > 0 && mode == MODE_APPLY && CONTIG && TC == 1 && a.n >= (NT / TC) * S))
+        return hipErrorInvalidValue;
     if (a.nops == 2) return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 2>(a, mode, false, st);
     return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 1>(a, mode, multi, st);
 }
@@ -830,7 +849,7 @@ hipError_t launch_line_pass_pipe_t(const PassArgs &a, int vid, hipStream_t st)
 // ------------------------------------------------------------------------------------------
 // Batched launches (contiguous variants only)
 // ------------------------------------------------------------------------------------------
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT>
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL>
 static hipError_t launch_batch_shape(const BatchLaunch &b, hipStream_t st)
 {
     constexpr Variant V{S, TC, CONTIG, NT};
@@ -841,19 +860,19 @@ static hipError_t launch_batch_shape(const BatchLaunch &b, hipStream_t st)
         const T *v = (const T *)b.v;
         T *o = (T *)b.out;
         if (b.mode == MODE_FUSED)
-            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT>), grid, block, 0, st, b.table,
+            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, FULL>), grid, block, 0, st, b.table,
                                b.work, b.nwork, v, o, b.g, b.ws);
         else if (b.mode == MODE_AGG)
-            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT>), grid, block, 0, st, b.table,
+            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, FULL>), grid, block, 0, st, b.table,
                                b.work, b.nwork, v, o, b.g, b.ws);
         else
-            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT>), grid, block, 0, st, b.table,
+            hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, FULL>), grid, block, 0, st, b.table,
                                b.work, b.nwork, v, o, b.g, b.ws);
         return hipGetLastError();
     }
 }
 
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT>
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL>
 static int batch_occupancy_shape(int mode)
 {
     constexpr Variant V{S, TC, CONTIG, NT};
@@ -864,35 +883,35 @@ static int batch_occupancy_shape(int mode)
         hipError_t e;
         if (mode == MODE_FUSED)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT>), NT, 0);
+                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_FUSED, NT, FULL>), NT, 0);
         else if (mode == MODE_AGG)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT>), NT, 0);
+                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, FULL>), NT, 0);
         else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT>), NT, 0);
+                &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, FULL>), NT, 0);
         return e == hipSuccess ? occ : 0;
     }
 }
 
-template <typename T, int ORDER>
+template <typename T, int ORDER, bool FULL>
 hipError_t launch_line_pass_batch_t(const BatchLaunch &b, int vid, hipStream_t st)
 {
     switch (vid) {
 #define SC_CASE(id, S, TC, CONTIG, NT) \
-    case id: return launch_batch_shape<T, ORDER, S, TC, CONTIG, NT>(b, st);
+    case id: return launch_batch_shape<T, ORDER, S, TC, CONTIG, NT, FULL>(b, st);
         SC_VARIANTS(SC_CASE)
 #undef SC_CASE
     }
     return hipErrorInvalidValue;
 }
 
-template <typename T, int ORDER>
+template <typename T, int ORDER, bool FULL>
 int line_pass_batch_occupancy_t(int vid, int mode)
 {
     switch (vid) {
 #define SC_CASE(id, S, TC, CONTIG, NT) \
-    case id: return batch_occupancy_shape<T, ORDER, S, TC, CONTIG, NT>(mode);
+    case id: return batch_occupancy_shape<T, ORDER, S, TC, CONTIG, NT, FULL>(mode);
         SC_VARIANTS(SC_CASE)
 #undef SC_CASE
     }

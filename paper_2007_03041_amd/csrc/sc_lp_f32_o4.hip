@@ -4,6 +4,6 @@
 
 namespace scx {
 template hipError_t launch_line_pass_t<float, 4, false>(const PassArgs &, int, int, bool, hipStream_t);
-template hipError_t launch_line_pass_batch_t<float, 4>(const BatchLaunch &, int, hipStream_t);
-template int line_pass_batch_occupancy_t<float, 4>(int, int);
+template hipError_t launch_line_pass_batch_t<float, 4, false>(const BatchLaunch &, int, hipStream_t);
+template int line_pass_batch_occupancy_t<float, 4, false>(int, int);
 }  // namespace scx

@@ -4,6 +4,6 @@
 
 namespace scx {
 template hipError_t launch_line_pass_t<double, 6, false>(const PassArgs &, int, int, bool, hipStream_t);
-template hipError_t launch_line_pass_batch_t<double, 6>(const BatchLaunch &, int, hipStream_t);
-template int line_pass_batch_occupancy_t<double, 6>(int, int);
+template hipError_t launch_line_pass_batch_t<double, 6, false>(const BatchLaunch &, int, hipStream_t);
+template int line_pass_batch_occupancy_t<double, 6, false>(int, int);
 }  // namespace scx

@@ -578,3 +578,61 @@ def test_single_pass_bounded_wait_gives_up_with_nan(gpu_lib, monkeypatch):
     ref = oracle.apply_invL(ogrid(g), 1, "0", 4, 40.0, v)
     got = host(sc.apply_invL(dev(v), g, 1, "0", 4, 40.0))
     assert err(got, ref, np.abs(ref).max()) < TOL
+
+
+# ------------------------------------------------------------------------------ windowed chunk carries
+WINDOW_CASES = [
+    (3 * 8192 + 500, "periodic", 1.0),
+    (3 * 8192 + 500, "dirichlet", 1.0),
+    (2 * 8192 + 200, "periodic", 0.4),   # K = 104
+    (2 * 8192 + 200, "dirichlet", 0.4),
+    (40000, "periodic", 2.0),
+    (40000, "dirichlet", 0.33),          # K = 127
+]
+
+
+@pytest.mark.parametrize("n,bc,nu", WINDOW_CASES)
+def test_windowed_chunk_carries(gpu_lib, n, bc, nu, monkeypatch):
+    """Chunked x lines whose decay over K = ceil(60 ln 2 / nu) <= 128 points is below 2^-60: one apply
+    launch whose carries are the sweeps over the K points beyond each chunk.  Against the oracle
+    (1e-12) and against the exact aggregate + apply launches (SC_WINDOW=0) to 1e-15 of the result."""
+    sc = gpu_lib
+    lines = 3
+    v = W.random_field((lines, n), index=90 + n % 97)
+    g = Grid((n, lines), (0.0, 0.0), (1.0, 1.0), (bc, "periodic"))
+    gv = np.random.default_rng(4).uniform(-1, 1, (lines, 2)) if bc == "dirichlet" else None
+    alpha = nu / g.dx(0)
+    for op in OPS:
+        ref = oracle.apply_invL(ogrid(g), 0, op, 6, alpha, v, gv)
+        sc.timing_reset()
+        sc.timing_select(None)
+        sc.timing_enable(True)
+        got = host(sc.apply_invL(dev(v), g, 0, op, 6, alpha, g=None if gv is None else dev(gv)))
+        sc.timing_enable(False)
+        names = set(sc.timing_read())
+        assert names == {"line_pass_apply_x"}, names  # the windowed form ran: no aggregate launch
+        assert err(got, ref, np.abs(ref).max()) < TOL, op
+        monkeypatch.setenv("SC_WINDOW", "0")
+        exact = host(sc.apply_invL(dev(v), g, 0, op, 6, alpha, g=None if gv is None else dev(gv)))
+        monkeypatch.delenv("SC_WINDOW")
+        assert err(got, exact, np.abs(exact).max()) < 1e-15 * 8, op
+        refd = oracle.apply_D_partial_sum(ogrid(g), 0, op, 6, alpha, 1, 1.0, v, gv)
+        gotd = host(sc.apply_D_partial_sum(dev(v), g, 0, op, 6, alpha, 1, 1.0, g=None if gv is None else dev(gv)))
+        assert err(gotd, refd, np.abs(v).max()) < TOL, op
+
+
+def test_windowed_carries_not_taken_when_the_window_is_long(gpu_lib):
+    """nu = 0.2 (K = 208 > 128), or a last chunk shorter than K: the exact aggregate + apply launches."""
+    sc = gpu_lib
+    for n, nu in ((3 * 8192 + 500, 0.2), (2 * 8192 + 40, 1.0)):
+        v = W.random_field((2, n), index=91)
+        g = Grid((n, 2), (0.0, 0.0), (1.0, 1.0))
+        alpha = nu / g.dx(0)
+        sc.timing_reset()
+        sc.timing_select(None)
+        sc.timing_enable(True)
+        got = host(sc.apply_invL(dev(v), g, 0, "0", 6, alpha))
+        sc.timing_enable(False)
+        assert "line_pass_agg_x" in set(sc.timing_read()), n
+        ref = oracle.apply_invL(ogrid(g), 0, "0", 6, alpha, v)
+        assert err(got, ref, np.abs(ref).max()) < TOL
