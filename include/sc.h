@@ -16,8 +16,11 @@
  * Memory and ownership
  *   - All array pointers are DEVICE pointers owned by the caller (hipMalloc or torch tensors),
  *     dense, C order, axis 0 (x) contiguous: element (i0, i1, i2) at i0 + n0*(i1 + n1*i2).
- *   - Pointers to arrays of the data type must be aligned to the element size; the library never
- *     allocates device memory and keeps no state between calls except read-only tables.
+ *   - Pointers to arrays of the data type must be aligned to the element size.  The library
+ *     allocates no device memory and keeps no state between calls except read-only tables, with
+ *     one exception: a batch plan (sc_batch_plan_create, sc_batch_tune) holds its launch tables
+ *     in device memory it allocates (hipMalloc) and frees in sc_batch_plan_destroy; rebuilding them
+ *     (creation, tuning) synchronises the device.
  *   - Every call is asynchronous on `stream` (0 = the null stream); SC_OK means "validated and
  *     enqueued".  Device-side faults surface at the caller's next synchronisation.
  *   - `out` must not overlap `v`.  Workspace buffers (`ws`) are caller-owned device memory of at
@@ -222,14 +225,25 @@ sc_status sc_batch_apply(sc_batch_plan plan, const void *v, void *out, const dou
 /* The same results through one sc_apply_invL / sc_apply_D_partial_sum call per instance. */
 sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws,
                                       size_t ws_bytes, sc_stream_t stream);
-/* Autotuner: times every candidate tile shape (persistent or one workgroup per work item) on each
- * class of the plan's instances, `reps` runs each, on the caller's arrays (out is overwritten),
- * keeps the fastest per class for this plan and for plans created later in the process.
+/* Autotuner: times every candidate tile shape (chunk length and lines per tile of the x-line
+ * variants; persistent or one workgroup per work item; windowed or exact chunk carries where the
+ * windowed ones apply) on each class of the plan's instances, `reps` runs each, on the caller's
+ * arrays (out is overwritten), keeps the fastest per class for this plan and for plans created
+ * later in the process (sc_batch_tune_export saves the table).
  * Synchronises `stream`; needs ws_bytes >= sc_batch_workspace_bytes(plan). */
 sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws, size_t ws_bytes,
                         int reps, sc_stream_t stream);
 /* JSON description of the plan's launches and tile shapes; returns its length (buf may be NULL). */
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
+/* The autotuner's table of this process as text, one class a line: "elem order nbits multi variant
+ * persistent exact" (elem 8 or 4 bytes; nbits = ceil(log2 n); multi = nlines >= 4; exact = 1: exact
+ * chunk carries where the windowed ones would apply).  Returns its length; writes at most len - 1
+ * characters and a terminating 0 to buf (buf may be NULL). */
+int sc_batch_tune_export(char *buf, int len);
+/* Merges such a table (e.g. saved from an earlier process) into this process's; plans created
+ * afterwards use it.  Rejects the whole text with SC_ERR_ARG if a line is malformed or names a
+ * shape not built for its element type. */
+sc_status sc_batch_tune_import(const char *text);
 
 /* ------------------------------------------------------------------------------------------------
  * Nonlinear Hamilton-Jacobi equation u_t + H(u_x, u_y) = S on a periodic 2-D grid (FP64,

@@ -35,7 +35,8 @@ SYMBOLS = ("sc_local_quad", "sc_sweep_LR", "sc_apply_invL", "sc_apply_D_partial_
            "sc_batch_elements", "sc_batch_apply", "sc_batch_apply_per_instance", "sc_batch_tune",
            "sc_batch_describe", "sc_hj_workspace_bytes", "sc_hj_init", "sc_hj_step", "sc_hj_harvest",
            "sc_mlp_param_count", "sc_mlp_forward", "sc_mlp_grad_workspace_bytes", "sc_mlp_grad", "sc_mlp_adam",
-           "sc_apply_invL_noalloc", "sc_apply_invL_nn", "sc_chunk_points")
+           "sc_apply_invL_noalloc", "sc_apply_invL_nn", "sc_chunk_points", "sc_batch_tune_export",
+           "sc_batch_tune_import")
 # fixed scratch of sc_apply_invL_noalloc (SC_NOALLOC_SCRATCH_BYTES in include/sc.h)
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -152,6 +153,10 @@ def load():
     lib.sc_batch_tune.argtypes = [bp, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
     lib.sc_batch_describe.argtypes = [bp, c_char_p, c_int]
     lib.sc_batch_describe.restype = c_int
+    lib.sc_batch_tune_export.argtypes = [c_char_p, c_int]
+    lib.sc_batch_tune_export.restype = c_int
+    lib.sc_batch_tune_import.argtypes = [c_char_p]
+    lib.sc_batch_tune_import.restype = c_int
     hp = POINTER(sc_hj_params)
     lib.sc_hj_workspace_bytes.argtypes = [gp]
     lib.sc_hj_workspace_bytes.restype = c_size_t
@@ -402,6 +407,24 @@ def timing_read(max_entries: int = 32):
     cnt = (c_int * max_entries)()
     m = lib.sc_timing_read(ctypes.cast(names, POINTER(c_char * 64)), ms, cnt, max_entries)
     return {bytes(names[i]).split(b"\0", 1)[0].decode(): (ms[i], cnt[i]) for i in range(m)}
+
+
+def batch_tune_save(path: str) -> int:
+    """Writes the autotuner's table of this process to ``path`` (text); returns the classes saved."""
+    lib = load()
+    n = lib.sc_batch_tune_export(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.sc_batch_tune_export(buf, n + 1)
+    with open(path, "w") as f:
+        f.write(buf.value.decode())
+    return buf.value.count(b"\n")
+
+
+def batch_tune_load(path: str) -> None:
+    """Merges a table written by ``batch_tune_save`` into this process's autotuner table."""
+    with open(path) as f:
+        text = f.read()
+    _check(load().sc_batch_tune_import(text.encode()))
 
 
 class BatchPlan:

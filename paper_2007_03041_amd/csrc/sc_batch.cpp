@@ -37,6 +37,7 @@ const int kBatchVariants[] = {14, 0, 10, 1, 16, 9, 2, 3, 15};
 struct Choice {
     int vid = -1;
     int persistent = 0;
+    int exact = 0;  // 1: exact chunk carries even where the windowed carries apply
 };
 
 struct ClassKey {
@@ -175,7 +176,7 @@ sc_status build(sc_batch_plan p)
         b.agg_off = b.carry_off = 0;
         int chunked = a.nchunks > 1 ? 1 : 0;
         if (chunked) {
-            const int K = window_k(a, p->order, V, false);
+            const int K = ch.exact ? 0 : window_k(a, p->order, V, false);
             if (K > 0) {
                 // windowed carries: the apply launch alone, no workspace
                 a.win_k = K;
@@ -500,8 +501,26 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
         Choice best_c = plan->choice[kv.second[0]];
         for (int vid : kBatchVariants) {
             if (!variant_built(vid, plan->elem)) continue;
-            for (int pers = 0; pers < 2; ++pers) {
-                for (auto &c : sub.choice) c = Choice{vid, pers};
+            for (int cand = 0; cand < 4; ++cand) {
+                const int pers = cand & 1, exact = cand >> 1;
+                // the exact carries are a separate candidate only where the windowed ones apply
+                if (exact) {
+                    bool any = false;
+                    for (int i : kv.second) {
+                        const sc_batch_item &it = plan->items[i];
+                        PassArgs a;
+                        std::memset(&a, 0, sizeof(a));
+                        a.n = it.n;
+                        a.stride = 1;
+                        a.nlines = it.nlines;
+                        a.nops = 1;
+                        a.nchunks = (it.n + variant(vid).C() - 1) / variant(vid).C();
+                        fill_op(&a.ops[0], it.op, plan->order, it.alpha, item_axis(it), vid, 1.0, it.k);
+                        any = any || window_k(a, plan->order, variant(vid), false) > 0;
+                    }
+                    if (!any) continue;
+                }
+                for (auto &c : sub.choice) c = Choice{vid, pers, exact};
                 s = build(&sub);
                 if (s != SC_OK) break;
                 hipError_t e = enqueue(&sub, v, out, g, ws, st, false);  // warm-up
@@ -517,7 +536,7 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
                 }
                 if (ms < best) {
                     best = ms;
-                    best_c = Choice{vid, pers};
+                    best_c = Choice{vid, pers, exact};
                 }
             }
             if (s != SC_OK) break;
@@ -539,18 +558,68 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
     return build(plan);
 }
 
+int sc_batch_tune_export(char *buf, int len)
+{
+    std::string txt;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto &kv : g_tuned) {
+            char line[96];
+            std::snprintf(line, sizeof(line), "%d %d %d %d %d %d %d\n", kv.first.elem, kv.first.order, kv.first.nbits,
+                          kv.first.multi, kv.second.vid, kv.second.persistent, kv.second.exact);
+            txt += line;
+        }
+    }
+    if (buf && len > 0) std::snprintf(buf, (size_t)len, "%s", txt.c_str());
+    return (int)txt.size();
+}
+
+sc_status sc_batch_tune_import(const char *text)
+{
+    if (!text) return fail(SC_ERR_ARG, "text is NULL");
+    std::map<ClassKey, Choice> got;
+    const char *p = text;
+    int lineno = 0;
+    while (*p) {
+        const char *e = std::strchr(p, '\n');
+        const std::string line(p, e ? (size_t)(e - p) : std::strlen(p));
+        p = e ? e + 1 : p + line.size();
+        ++lineno;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        ClassKey k{};
+        Choice c;
+        char extra = 0;
+        if (std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %c", &k.elem, &k.order, &k.nbits, &k.multi, &c.vid,
+                        &c.persistent, &c.exact, &extra) != 7)
+            return fail(SC_ERR_ARG, "tune table line " + std::to_string(lineno) + ": expected 7 integers");
+        bool known = false;
+        for (int v : kBatchVariants) known = known || v == c.vid;
+        if ((k.elem != 4 && k.elem != 8) || (k.order != 4 && k.order != 6) || k.nbits < 0 || k.nbits > 31 ||
+            (k.multi != 0 && k.multi != 1) || !known || !variant_built(c.vid, k.elem) ||
+            (c.persistent != 0 && c.persistent != 1) || (c.exact != 0 && c.exact != 1))
+            return fail(SC_ERR_ARG, "tune table line " + std::to_string(lineno) + ": value out of range");
+        got[k] = c;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &kv : got) g_tuned[kv.first] = kv.second;
+    return SC_OK;
+}
+
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len)
 {
     if (!plan) return -1;
-    std::map<std::tuple<int, int>, int> use;
-    for (const Choice &c : plan->choice) use[std::make_tuple(c.vid, c.persistent)] += 1;
+    std::map<std::tuple<int, int, int>, int> use;
+    for (const Choice &c : plan->choice) use[std::make_tuple(c.vid, c.persistent, c.exact)] += 1;
     std::string js = "{\"launches\": " + std::to_string(plan->launches.size()) + ", \"shapes\": [";
     bool first = true;
     for (auto &kv : use) {
         const Variant &V = variant(std::get<0>(kv.first));
         char tmp[200];
-        std::snprintf(tmp, sizeof(tmp), "%s{\"variant\": %d, \"S\": %d, \"TC\": %d, \"NT\": %d, \"chunk\": %d, \"persistent\": %d, \"instances\": %d}",
-                      first ? "" : ", ", std::get<0>(kv.first), V.S, V.TC, V.NT, V.C(), std::get<1>(kv.first), kv.second);
+        std::snprintf(tmp, sizeof(tmp),
+                      "%s{\"variant\": %d, \"S\": %d, \"TC\": %d, \"NT\": %d, \"chunk\": %d, \"persistent\": %d, "
+                      "\"exact_carries\": %d, \"instances\": %d}",
+                      first ? "" : ", ", std::get<0>(kv.first), V.S, V.TC, V.NT, V.C(), std::get<1>(kv.first),
+                      std::get<2>(kv.first), kv.second);
         js += tmp;
         first = false;
     }

@@ -182,3 +182,22 @@ def test_nearest_neighbour_entry_point_validation():
     # whole-chunk blocks pass validation (then fail on the missing workspace)
     assert call(1, 1024) == sc.SC_ERR_WORKSPACE
     assert call(0, 8192) == sc.SC_ERR_WORKSPACE
+
+
+def test_batch_tune_table_round_trip(tmp_path):
+    """The autotuner's table is plain text: a table imported is exported back unchanged (merged
+    with what the process held), and malformed or unbuilt entries are refused whole."""
+    lib = sc.load()
+    path = tmp_path / "tune.txt"
+    text = "8 6 14 1 14 1 0\n4 6 13 0 3 0 1\n"
+    path.write_text(text)
+    sc.batch_tune_load(str(path))
+    out = tmp_path / "out.txt"
+    sc.batch_tune_save(str(out))
+    lines = set(out.read_text().splitlines())
+    assert set(text.splitlines()) <= lines
+    for bad in ("8 6 14 1 14 1\n", "8 6 14 1 99 0 0\n", "8 5 14 1 14 0 0\n", "8 6 14 1 14 0 0 7\n"):
+        assert lib.sc_batch_tune_import(bad.encode()) == sc.SC_ERR_ARG, bad
+    # a refused text changes nothing
+    sc.batch_tune_save(str(out))
+    assert set(out.read_text().splitlines()) == lines
