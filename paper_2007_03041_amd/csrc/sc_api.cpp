@@ -354,7 +354,7 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
             a.ops[0].inv1mmu = 1.0;
             a.ops[0].dir2inv = 2.0;
             e = timed(kApply[dim], st, [&](const char **) {
-                return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_APPLY, false, st);
+                return scx::launch_line_pass(a, elem, order, vid, scx::LMODE_WIN, false, st);
             });
             if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
             return SC_OK;

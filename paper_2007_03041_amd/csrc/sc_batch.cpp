@@ -243,7 +243,7 @@ sc_status build(sc_batch_plan p)
                     w[(ragged && last) ? 0 : 1].push_back(BatchWork{i, 0, t});
                 }
             }
-            L.mode = phase == 0 ? LMODE_FUSED : phase == 1 ? LMODE_AGG : LMODE_APPLY;
+            L.mode = phase == 0 ? LMODE_FUSED : phase == 1 ? LMODE_AGG : chunked == 2 ? LMODE_WIN : LMODE_APPLY;
             for (int full = 1; full >= 0; --full) {
                 if (w[full].empty()) continue;
                 L.full = full;
@@ -287,8 +287,11 @@ hipError_t enqueue(sc_batch_plan p, const void *v, void *out, const double *g, v
         if (time_it) {
             // timing names carry the launch's shape: batch_<phase>_v<variant><p: persistent, o: one
             // workgroup per item>[f: tiles that end inside their line]
-            std::string nm = L.kind == 1 ? "batch_chunk_carry"
-                                         : L.mode == LMODE_FUSED ? "batch_fused" : L.mode == LMODE_AGG ? "batch_agg" : "batch_apply";
+            std::string nm = L.kind == 1                ? "batch_chunk_carry"
+                             : L.mode == LMODE_FUSED ? "batch_fused"
+                             : L.mode == LMODE_AGG   ? "batch_agg"
+                             : L.mode == LMODE_WIN   ? "batch_window"
+                                                     : "batch_apply";
             if (L.kind == 0) nm += "_v" + std::to_string(L.vid) + (L.grid < L.nwork ? "p" : "o") + (L.full ? "f" : "");
             e = timed(nm.c_str(), st, run);
         } else {

@@ -263,8 +263,7 @@ hipError_t launch_line_pass(const PassArgs &a, int elem, int order, int vid, int
     // the per-point end rules keep fewer registers live and reach a higher occupancy.  Windowed
     // applies take a ragged last chunk as the full tile ending at the line's end, so all their tiles
     // are full.
-    const bool full = a.n % variant(vid).C() == 0 || (a.win_k > 0 && mode == LMODE_APPLY && variant(vid).contig &&
-                                                      variant(vid).TC == 1 && a.n >= variant(vid).C());
+    const bool full = a.n % variant(vid).C() == 0 || (mode == LMODE_WIN && a.n >= variant(vid).C());
     if (elem == 8) {
         if (order == 4)
             return full ? launch_line_pass_t<double, 4, true>(a, vid, mode, multi, st)

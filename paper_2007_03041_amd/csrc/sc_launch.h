@@ -7,7 +7,7 @@
 
 namespace scx {
 
-enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2, LMODE_SINGLE = 3 };
+enum { LMODE_FUSED = 0, LMODE_AGG = 1, LMODE_APPLY = 2, LMODE_SINGLE = 3, LMODE_WIN = 4 };
 
 int num_variants();
 const Variant &variant(int id);

@@ -52,7 +52,7 @@
 
 namespace scx {
 
-enum { MODE_FUSED = 0, MODE_AGG = 1, MODE_APPLY = 2, MODE_SINGLE = 3 };
+enum { MODE_FUSED = 0, MODE_AGG = 1, MODE_APPLY = 2, MODE_SINGLE = 3, MODE_WIN = 4 };
 
 // Single-pass chunked launches: the chunk totals slots hold this bit pattern (a signalling NaN, which
 // arithmetic never produces) until their tile publishes them.
@@ -655,7 +655,7 @@ line_pass(const PassArgs a)
     constexpr bool pipe_first = false;
     constexpr int64_t pipe_next = -1;
     const Ptrs pt{a.v, a.acc, a.out, a.g, a.agg, a.carry};
-    int64_t blk = (MODE == MODE_APPLY) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    int64_t blk = (MODE == MODE_APPLY || MODE == MODE_WIN) ? xcd_grouped(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     if constexpr (MODE == MODE_SINGLE) {
         // tiles are claimed in order (line group by line group, its chunks in turn), so every tile
         // a tile waits for has been claimed by a running workgroup or will be by the next one to start
@@ -709,7 +709,7 @@ line_pass_pipe(const PassArgs a_arg, int64_t ntiles)
 // 168 VGPRs (3 waves per SIMD) for general tiles and for FP64 applies, whose 128-register form
 // spills (3.43 vs 3.06 ms); 128 for the rest (FP32 applies 2.29 vs 2.59 ms).
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FULL && (MODE != MODE_APPLY || sizeof(T) == 4)) ? 4 : 3)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FULL && ((MODE != MODE_APPLY && MODE != MODE_WIN) || sizeof(T) == 4)) ? 4 : 3)))
 line_pass_batch(const BatchArgs *__restrict__ table,
                                                      const BatchWork *__restrict__ work, int64_t nwork,
                                                      const T *vbase, T *obase, const double *gbase, double *wsbase)
@@ -770,7 +770,12 @@ static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStrea
         else if (mode == MODE_SINGLE)
             hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_SINGLE, NT, NOPS, false, FULL>), grid, dim3(NT), 0,
                                st, a);
-        else
+        else if (mode == MODE_WIN) {
+            if constexpr (CONTIG && TC == 1 && NOPS == 1)
+                hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_WIN, NT, 1, false, FULL>), grid, dim3(NT), 0, st, a);
+            else
+                return hipErrorInvalidValue;
+        } else
             hipLaunchKernelGGL((line_pass<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, NOPS, false, FULL>), grid, dim3(NT), 0, st,
                                a);
         return hipGetLastError();
@@ -780,8 +785,7 @@ static hipError_t launch_shape(const PassArgs &a, int mode, bool multi, hipStrea
 template <typename T, int ORDER, bool FULL, int S, int TC, bool CONTIG, int NT>
 static hipError_t launch_variant(const PassArgs &a, int mode, bool multi, hipStream_t st)
 {
-    if (FULL && a.n % ((NT / TC) * S) != 0 && !(a.win_k > 0 && mode == MODE_APPLY && CONTIG && TC == 1 && a.n >= (NT / TC) * S))
-        return hipErrorInvalidValue;
+    if (FULL && a.n % ((NT / TC) * S) != 0 && !(mode == MODE_WIN && a.n >= (NT / TC) * S)) return hipErrorInvalidValue;
     if (a.nops == 2) return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 2>(a, mode, false, st);
     return launch_shape<T, ORDER, FULL, S, TC, CONTIG, NT, 1>(a, mode, multi, st);
 }
@@ -865,7 +869,13 @@ static hipError_t launch_batch_shape(const BatchLaunch &b, hipStream_t st)
         else if (b.mode == MODE_AGG)
             hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, FULL>), grid, block, 0, st, b.table,
                                b.work, b.nwork, v, o, b.g, b.ws);
-        else
+        else if (b.mode == MODE_WIN) {
+            if constexpr (TC == 1)
+                hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_WIN, NT, FULL>), grid, block, 0, st, b.table,
+                                   b.work, b.nwork, v, o, b.g, b.ws);
+            else
+                return hipErrorInvalidValue;
+        } else
             hipLaunchKernelGGL((line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, FULL>), grid, block, 0, st, b.table,
                                b.work, b.nwork, v, o, b.g, b.ws);
         return hipGetLastError();
@@ -887,7 +897,14 @@ static int batch_occupancy_shape(int mode)
         else if (mode == MODE_AGG)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_AGG, NT, FULL>), NT, 0);
-        else
+        else if (mode == MODE_WIN) {
+            if constexpr (TC == 1)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_WIN, NT, FULL>), NT,
+                    0);
+            else
+                return 0;
+        } else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &occ, reinterpret_cast<const void *>(&line_pass_batch<T, ORDER, S, TC, CONTIG, MODE_APPLY, NT, FULL>), NT, 0);
         return e == hipSuccess ? occ : 0;
