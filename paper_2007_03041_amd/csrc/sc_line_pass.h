@@ -706,10 +706,11 @@ line_pass_pipe(const PassArgs a_arg, int64_t ntiles)
 // ... of the list; each item is one tile of one instance, whose argument block (coefficients, sizes,
 // element offsets of its arrays) lives in a device table.  Items of one launch share the tile shape.
 // FULL: every item's tile ends inside its line.  Register budgets as measured on the ragged batch:
-// 168 VGPRs (3 waves per SIMD) for general tiles and for FP64 applies, whose 128-register form
-// spills (3.43 vs 3.06 ms); 128 for the rest (FP32 applies 2.29 vs 2.59 ms).
+// 168 VGPRs (3 waves per SIMD) for general tiles and for FP64 exact-carry applies, whose
+// 128-register form spills (3.43 vs 3.06 ms); 128 for the rest (FP32 applies 2.29 vs 2.59 ms,
+// FP64 windowed applies 3.02 vs 2.91 ms).
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FULL && ((MODE != MODE_APPLY && MODE != MODE_WIN) || sizeof(T) == 4)) ? 4 : 3)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FULL && (MODE != MODE_APPLY || sizeof(T) == 4)) ? 4 : 3)))
 line_pass_batch(const BatchArgs *__restrict__ table,
                                                      const BatchWork *__restrict__ work, int64_t nwork,
                                                      const T *vbase, T *obase, const double *gbase, double *wsbase)
