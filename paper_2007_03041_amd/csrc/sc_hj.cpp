@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -40,7 +41,10 @@ HjLayout hj_layout(const sc_grid *g)
         off += f;
     }
     L.part = off;
-    off += round256(sizeof(double) * (size_t)L.nblocks);
+    // per-block wave-speed maxima: of the update's blocks, or of the fused passes' workgroups
+    const int64_t nparts = std::max<int64_t>(L.nblocks, hj_fused_blocks(g->n[0], g->n[1], 0) +
+                                                            hj_fused_blocks(g->n[0], g->n[1], 1));
+    off += round256(sizeof(double) * (size_t)nparts);
     L.stats = off;
     off += round256(sizeof(double) * 6 * (size_t)L.nblocks);
     L.chunk = off;
@@ -120,6 +124,33 @@ HjQuadArgs quad_args(const sc_grid *g, const sc_hj_params *p, int axis)
     return Q;
 }
 
+// The fused two-pass step applies to the separable quadratic Hamiltonian with linear or WENO-Z
+// weights where the sweeps' decay over the window, d^{HJF_KW}, is below 2^-60 on both axes.
+// SC_HJ_FUSED=0 always takes the step of separate launches.
+bool hj_fused_ok(const sc_grid *g, const sc_hj_params *p, const HjStepArgs &A)
+{
+    const char *env = std::getenv("SC_HJ_FUSED");
+    if (env && env[0] == '0') return false;
+    if (p->weights == HJ_LEARNED || p->hamiltonian != HJ_H_QUADRATIC) return false;
+    const double nu_min = std::min(A.alpha_x * A.dx, A.alpha_y * A.dy);
+    (void)g;
+    return nu_min * HJF_KW >= 60.0 * std::log(2.0);
+}
+
+HjFusedArgs fused_args(const HjStepArgs &A)
+{
+    HjFusedArgs F;
+    std::memset(&F, 0, sizeof(F));
+    for (int ax = 0; ax < 2; ++ax) {
+        const double nu = ax == 0 ? A.alpha_x * A.dx : A.alpha_y * A.dy;
+        F.alpha[ax] = ax == 0 ? A.alpha_x : A.alpha_y;
+        F.d[ax] = std::exp(-nu);
+        for (int t = 0; t <= HJF_PPL; ++t) F.dpow[ax][t] = std::exp(-nu * t);
+        for (int k = 0; k < 6; ++k) F.dscan[ax][k] = std::exp(-nu * (double)HJF_PPL * (double)(1 << k));
+    }
+    return F;
+}
+
 }  // namespace
 
 extern "C" {
@@ -170,6 +201,34 @@ sc_status sc_hj_step(const sc_grid *grid, const sc_hj_params *p, int nsteps, voi
     const HjStepArgs A = step_args(grid, p);
     const HjQuadArgs Q[2] = {quad_args(grid, p, 0), quad_args(grid, p, 1)};
     const double alpha = A.alpha_x;
+    if (hj_fused_ok(grid, p, A)) {
+        // two passes a step, alternating between u and a workspace field: x: dst = src - dt Hx(src);
+        // y: dst -= dt Hy(src).  An odd step count ends with a copy back into u.
+        const HjFusedArgs F = fused_args(A);
+        const int64_t nbx = hj_fused_blocks(A.nx, A.ny, 0), nby = hj_fused_blocks(A.nx, A.ny, 1);
+        double *bufs[2] = {(double *)u, D[0]};
+        for (int step = 0; step < nsteps; ++step) {
+            const double *src = bufs[step & 1];
+            double *dst = bufs[(step + 1) & 1];
+            hipError_t e = timed("hj_fused_x", st, [&](const char **) {
+                return launch_hj_fused_pass(0, p->weights, src, nullptr, dst, Q[0], F, A, state, part, st);
+            });
+            if (e == hipSuccess)
+                e = timed("hj_fused_y", st, [&](const char **) {
+                    return launch_hj_fused_pass(1, p->weights, src, dst, dst, Q[1], F, A, state, part + nbx, st);
+                });
+            if (e == hipSuccess)
+                e = timed("hj_finish_step", st, [&](const char **) {
+                    return launch_hj_finish(part, nbx + nby, stats, 0, A, state, 1, st);
+                });
+            if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        }
+        if (nsteps & 1) {
+            const hipError_t e = hipMemcpyAsync(u, D[0], fbytes, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("copy failed: ") + hipGetErrorString(e));
+        }
+        return SC_OK;
+    }
     for (int step = 0; step < nsteps; ++step) {
         for (int axis = 0; axis < 2; ++axis) {
             hipError_t e = timed("hj_weno_quad", st, [&](const char **) {

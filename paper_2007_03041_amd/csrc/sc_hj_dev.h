@@ -45,6 +45,25 @@ struct HjStepArgs {
     int32_t pad_;
 };
 
+// Fused step of the separable Hamiltonian (p^2 + q^2) / 2 (linear or WENO-Z weights): each wave owns
+// HJF_C points of one line plus HJF_KW window points on either side, over which the periodic
+// line's sweeps are summed from zero (taken where d^{HJF_KW} < 2^-60).
+constexpr int HJF_C = 512;
+constexpr int HJF_KW = 64;
+constexpr int HJF_PPL = (HJF_C + 2 * HJF_KW) / 64;  // points a lane sweeps
+constexpr int HJF_ROW = HJF_C + 2 * HJF_KW + 6;     // tile points per line (stencil halo of 3 each side)
+struct HjFusedArgs {
+    double alpha[2];             // per axis
+    double d[2];                 // e^{-alpha dx} per axis
+    double dpow[2][HJF_PPL + 1]; // d^t, t = 0..HJF_PPL
+    double dscan[2][6];          // d^{HJF_PPL 2^s}: decay across 2^s lanes
+};
+// the number of workgroups of the x and y passes (their wave-speed maxima go to part[])
+int64_t hj_fused_blocks(int64_t nx, int64_t ny, int axis);
+hipError_t launch_hj_fused_pass(int axis, int weights, const double *u, const double *w_in, double *out,
+                                const HjQuadArgs &Q, const HjFusedArgs &F, const HjStepArgs &A, const double *state,
+                                double *part, hipStream_t st);
+
 hipError_t launch_hj_weno_quad(int mode, const double *u, double *JL, double *JR, const HjQuadArgs &A,
                                const float *P, double *stats, hipStream_t st);
 hipError_t launch_hj_update(double *u, const double *DmX, const double *DpX, const double *DmY, const double *DpY,

@@ -395,6 +395,167 @@ __global__ void __launch_bounds__(256) hj_init_speed(const double *__restrict__ 
     if (tid == 0) part[blockIdx.x] = red[0];
 }
 
+// ------------------------------------------------------------------------------------------
+// Fused step of the separable Hamiltonian H(p, q) = (p^2 + q^2) / 2: its Lax-Friedrichs numerical
+// Hamiltonian splits into an x part (p_mean^2 / 2 + c (p- - p+) / 2) and a y part, so one step is
+// two line passes: along x, w = u - dt Hx; along y, u <- w - dt Hy, each computing its weights,
+// local integrals, sweeps and one-sided derivatives in registers.  One wave per line chunk of
+// HJF_C points; its lanes sweep HJF_PPL consecutive points each over the chunk and HJF_KW window
+// points on either side, and the sweeps of the periodic line are summed from zero at the window's
+// ends: the dropped remainder is below d^{HJF_KW} < 2^-60 of the result (Sec. 3.1, the N-N
+// criterion at that tolerance), so no wave needs another's totals.  AXIS 0: lines along x, TC of
+// them per workgroup, tile [line][point]; AXIS 1: TC adjacent y lines, tile [point][line] so the
+// loads and stores run along rows.
+// ------------------------------------------------------------------------------------------
+template <int AXIS, int TC, int MODE>
+__global__ void __launch_bounds__(TC * 64) hj_fused_pass(const double *__restrict__ u, const double *w_in,
+                                                         double *out, const HjQuadArgs Q, const HjFusedArgs F,
+                                                         const HjStepArgs A, const double *__restrict__ state,
+                                                         double *__restrict__ part)
+{
+    constexpr int LS = AXIS == 0 ? HJF_ROW : TC + 1;  // LDS stride: x between lines, y between points
+    __shared__ double tile[TC * HJF_ROW + (AXIS == 0 ? 0 : HJF_ROW)];
+    __shared__ double red[TC];
+    auto TI = [](int line, int q) { return AXIS == 0 ? line * LS + q : q * LS + line; };
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t n = AXIS == 0 ? A.nx : A.ny;       // points per line
+    const int64_t nlines = AXIS == 0 ? A.ny : A.nx;
+    const int64_t nch = (n + HJF_C - 1) / HJF_C;
+    const int64_t chunk = (int64_t)blockIdx.x % nch;
+    const int64_t line0 = ((int64_t)blockIdx.x / nch) * TC;
+    const int64_t c0 = chunk * HJF_C;
+    const int64_t q0 = c0 - HJF_KW - 3;  // line point of tile point 0 (wrapped below)
+    auto wrap = [n](int64_t p) {
+        p %= n;
+        return p < 0 ? p + n : p;
+    };
+    auto gidx = [&](int64_t line, int64_t p) { return AXIS == 0 ? line * A.nx + p : p * A.nx + line; };
+
+    // 1. the tile: TC lines x HJF_ROW points (lines past the grid read line 0; they store nothing)
+    if (AXIS == 0) {
+        const int64_t L = line0 + wv < nlines ? line0 + wv : 0;
+        for (int q = lane; q < HJF_ROW; q += 64) tile[TI(wv, q)] = u[gidx(L, wrap(q0 + q))];
+    } else {
+        for (int e = tid; e < TC * HJF_ROW; e += TC * 64) {
+            const int q = e / TC, cc = e % TC;
+            const int64_t L = line0 + cc < nlines ? line0 + cc : 0;
+            tile[TI(cc, q)] = u[gidx(L, wrap(q0 + q))];
+        }
+    }
+    __syncthreads();
+
+    // 2. this lane's points t = 0..PPL-1 sit at tile points 3 + lane PPL + t; v[k] = tile point
+    //    lane PPL + k, k = 0..PPL+5 (the stencil halo of 3 on either side)
+    constexpr int PPL = HJF_PPL;
+    double v[PPL + 6];
+#pragma unroll
+    for (int k = 0; k < PPL + 6; ++k) v[k] = tile[TI(wv, lane * PPL + k)];
+    const double alpha = F.alpha[AXIS], d = F.d[AXIS];
+    double JR[PPL], JL[PPL];
+#pragma unroll
+    for (int t = 0; t < PPL; ++t) {
+        // J_R from the nodes x_{i-3} .. x_{i+1}, J_L from the mirror x_{i+3} .. x_{i-1}
+        double sR[5], sL[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            sR[k] = v[t + k];
+            sL[k] = v[t + 6 - k];
+        }
+        double oR[3], oL[3];
+        if (MODE == HJ_LINEAR) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) oR[r] = oL[r] = Q.d[r];
+        } else {
+            wenoz(sR, Q.d, oR);
+            wenoz(sL, Q.d, oL);
+        }
+        double jr = 0.0, jl = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            double qR = 0.0, qL = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                qR = fma(Q.c[r][j], sR[r + j], qR);
+                qL = fma(Q.c[r][j], sL[r + j], qL);
+            }
+            jr = fma(oR[r], qR, jr);
+            jl = fma(oL[r], qL, jl);
+        }
+        JR[t] = jr;
+        JL[t] = jl;
+    }
+
+    // 3. sweeps: lane totals, their scans across the wave (decay d^{PPL} a lane), then the re-sweep
+    //    from the carry into the lane
+    double fR = 0.0, fL = 0.0;
+#pragma unroll
+    for (int t = 0; t < PPL; ++t) fR = fma(d, fR, JR[t]);
+#pragma unroll
+    for (int t = PPL - 1; t >= 0; --t) fL = fma(d, fL, JL[t]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int k = 1 << s;
+        const double yR = __shfl_up(fR, k, 64), yL = __shfl_down(fL, k, 64);
+        if (lane >= k) fR = fma(F.dscan[AXIS][s], yR, fR);
+        if (lane + k < 64) fL = fma(F.dscan[AXIS][s], yL, fL);
+    }
+    double cR = __shfl_up(fR, 1, 64), cL = __shfl_down(fL, 1, 64);
+    if (lane == 0) cR = 0.0;
+    if (lane == 63) cL = 0.0;
+    double IR[PPL];
+#pragma unroll
+    for (int t = 0; t < PPL; ++t) {
+        cR = fma(d, cR, JR[t]);
+        IR[t] = cR;
+    }
+
+    // 4. one-sided derivatives p- = alpha (u - I_R), p+ = -alpha (u - I_L), the x or y part of the
+    //    numerical Hamiltonian, the time step from the lagged speed, and the new values
+    const double c = state[HJ_S_C];
+    const double dt = hj_dt(A, state);
+    double m = 0.0, res[PPL];
+#pragma unroll
+    for (int t = PPL - 1; t >= 0; --t) {
+        cL = fma(d, cL, JL[t]);
+        const double ui = v[t + 3];
+        const double pm = alpha * (ui - IR[t]), pp = -alpha * (ui - cL);
+        const double pmean = 0.5 * (pm + pp);
+        const double H = 0.5 * pmean * pmean + c * 0.5 * (pm - pp);
+        res[t] = AXIS == 0 ? ui - dt * H : dt * H;
+        const int64_t p = c0 - HJF_KW + lane * PPL + t;  // line point (before the chunk: window only)
+        if (p >= c0 && p < c0 + HJF_C && p < n) m = fmax(m, fmax(fabs(pm), fabs(pp)));
+    }
+    if (line0 + wv >= nlines) m = 0.0;
+    // (each wave reads and writes only its own line of the tile)
+#pragma unroll
+    for (int t = 0; t < PPL; ++t) tile[TI(wv, 3 + lane * PPL + t)] = res[t];
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) m = fmax(m, __shfl_xor(m, k, 64));
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+
+    // 5. stores of the chunk's points, along rows: x writes w = u - dt Hx, y writes u = w - dt Hy
+    const int64_t cn = (c0 + HJF_C < n ? c0 + HJF_C : n) - c0;  // points of this chunk
+    if (AXIS == 0) {
+        if (line0 + wv < nlines)
+            for (int j = lane; j < cn; j += 64) out[gidx(line0 + wv, c0 + j)] = tile[TI(wv, 3 + HJF_KW + j)];
+    } else {
+        for (int e = tid; e < TC * cn; e += TC * 64) {
+            const int j = e / TC, cc = e % TC;
+            if (line0 + cc < nlines) {
+                const int64_t g = gidx(line0 + cc, c0 + j);
+                out[g] = w_in[g] - tile[TI(cc, 3 + HJF_KW + j)];
+            }
+        }
+    }
+    if (tid == 0) {
+        double M = 0.0;
+        for (int k = 0; k < TC; ++k) M = fmax(M, red[k]);
+        part[blockIdx.x] = M;
+    }
+}
+
 // One block: reduce the per-block maxima (and the proposer statistics), then advance the state.
 // mode 0: initialise (c = max, t = 0, counters = 0); mode 1: after an update (t += dt with the old c,
 // then c = max).  1024 threads with four independent loads in flight each, so the reduction of the
@@ -833,6 +994,38 @@ hipError_t launch_hj_finish(const double *part, int64_t nparts, const double *st
                             const HjStepArgs &A, double *state, int mode, hipStream_t st)
 {
     hipLaunchKernelGGL(hj_finish_step, dim3(1), dim3(HJ_FIN_THREADS), 0, st, part, nparts, stats, nstats, A, state, mode);
+    return hipGetLastError();
+}
+
+constexpr int HJF_TCX = 4, HJF_TCY = 16;
+
+int64_t hj_fused_blocks(int64_t nx, int64_t ny, int axis)
+{
+    const int64_t n = axis == 0 ? nx : ny, nlines = axis == 0 ? ny : nx;
+    const int TC = axis == 0 ? HJF_TCX : HJF_TCY;
+    return ((nlines + TC - 1) / TC) * ((n + HJF_C - 1) / HJF_C);
+}
+
+hipError_t launch_hj_fused_pass(int axis, int weights, const double *u, const double *w_in, double *out,
+                                const HjQuadArgs &Q, const HjFusedArgs &F, const HjStepArgs &A, const double *state,
+                                double *part, hipStream_t st)
+{
+    const dim3 grid((unsigned)hj_fused_blocks(A.nx, A.ny, axis));
+    if (axis == 0) {
+        if (weights == HJ_LINEAR)
+            hipLaunchKernelGGL((hj_fused_pass<0, HJF_TCX, HJ_LINEAR>), grid, dim3(HJF_TCX * 64), 0, st, u, w_in, out, Q, F,
+                               A, state, part);
+        else
+            hipLaunchKernelGGL((hj_fused_pass<0, HJF_TCX, HJ_WENOZ>), grid, dim3(HJF_TCX * 64), 0, st, u, w_in, out, Q, F,
+                               A, state, part);
+    } else {
+        if (weights == HJ_LINEAR)
+            hipLaunchKernelGGL((hj_fused_pass<1, HJF_TCY, HJ_LINEAR>), grid, dim3(HJF_TCY * 64), 0, st, u, w_in, out, Q, F,
+                               A, state, part);
+        else
+            hipLaunchKernelGGL((hj_fused_pass<1, HJF_TCY, HJ_WENOZ>), grid, dim3(HJF_TCY * 64), 0, st, u, w_in, out, Q, F,
+                               A, state, part);
+    }
     return hipGetLastError();
 }
 

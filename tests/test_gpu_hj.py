@@ -324,3 +324,49 @@ def test_learned_solver_matches_oracle_with_the_same_proposer(gpu_lib):
     u = torch.from_numpy(hj_u0(n)).cuda()
     s.run_to(u)
     assert np.abs(u.cpu().numpy() - ref).max() < 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("weights", ["linear", "wenoz"])
+@pytest.mark.parametrize("shape,steps", [((64, 64), 7), ((300, 200), 10), ((1100, 530), 5), ((2048, 2048), 3)])
+def test_fused_step_matches_the_separate_launches(gpu_lib, weights, shape, steps, monkeypatch):
+    """The two-pass step (x: w = u - dt Hx; y: u = w - dt Hy, sweeps summed over windows of 64 points
+    on either side of each 512-point chunk, nu = 1 here) against the step of separate launches
+    (SC_HJ_FUSED=0), both from the same state, odd and even step counts, lines of one and of several
+    chunks: the same solution to 1e-12 and the same lagged wave speed and time."""
+    n0, n1 = shape
+    x = np.arange(n0) * (L / n0)
+    y = np.arange(n1) * (L / n1)
+    u0 = np.sin(x)[None, :] + np.cos(2 * y)[:, None] + 0.3 * np.sin(x[None, :] + 3 * y[:, None])
+    res = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("SC_HJ_FUSED", fused)
+        s = sc.HJSolver((n0, n1), L=L, t_end=10.0, weights=weights)
+        u = torch.from_numpy(u0.copy()).cuda()
+        s.init(u)
+        sc.timing_reset()
+        sc.timing_select(None)
+        sc.timing_enable(True)
+        s.step(u, steps)
+        sc.timing_enable(False)
+        names = set(sc.timing_read())
+        assert ("hj_fused_x" in names) == (fused == "1"), names
+        res[fused] = (u.cpu().numpy(), s.read_state())
+    monkeypatch.delenv("SC_HJ_FUSED")
+    (a, sa), (b, sb) = res["1"], res["0"]
+    assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+    assert abs(sa["c"] - sb["c"]) < 1e-12 * sb["c"] and abs(sa["t"] - sb["t"]) < 1e-14 and sa["steps"] == steps
+
+
+def test_fused_step_not_taken_for_learned_weights_or_example3(gpu_lib):
+    for kw in (dict(weights="learned"), dict(weights="linear", hamiltonian="ex3"), dict(weights="linear", cfl=2.0)):
+        s = sc.HJSolver(64, L=L, t_end=1.0, **kw)
+        if kw.get("weights") == "learned":
+            s.mlp = torch.zeros(sc.load().sc_mlp_param_count(), dtype=torch.float32, device="cuda")
+        u = torch.from_numpy(hj_u0(64)).cuda()
+        s.init(u)
+        sc.timing_reset()
+        sc.timing_select(None)
+        sc.timing_enable(True)
+        s.step(u, 2)
+        sc.timing_enable(False)
+        assert "hj_fused_x" not in set(sc.timing_read()), kw
