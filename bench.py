@@ -540,7 +540,8 @@ def cpu_baseline(sc, torch, reps=10, warm=3):
 # counter ingestion: rocprofv3 --pmc summaries -> profiles/traffic_counters.json
 # ------------------------------------------------------------------------------------------------
 PASS_ORDER = {"heat3d_f64": ("line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z"),
-              "heat3d_mixed": ("line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z")}
+              "heat3d_mixed": ("line_pass_fused_x", "line_pass_fused_y", "line_pass_fused_z"),
+              "advdiff2d": ("line_pass_fused_x", "line_pass_agg_y", "line_pass_apply_y")}
 
 
 def _counter_means(path, counter, filt):

@@ -46,6 +46,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sc_device.h"
 #include "sc_launch.h"
@@ -423,7 +424,8 @@ template <typename T>
 __device__ __forceinline__ void load_lds16(const T *src, T *lds_dst)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0, 0);
+    // (cache policy nt: the pipelined strided tiles' operand is read once)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0, 2);
 #endif
 }
 
@@ -443,6 +445,13 @@ template <typename T>
 __device__ __forceinline__ T ldg(const T *p)
 {
     return *p;
+}
+
+// streaming load (non-temporal): operands that no other tile of the pass reads again
+template <typename T>
+__device__ __forceinline__ T ldg_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
 }
 
 // Value at point p of the line at `base`: periodic wrap, or for Dirichlet lines the extension of
@@ -481,10 +490,13 @@ constexpr int tile_fill(int order, int S, int TC, int NT) { return (TC * ((NT / 
 // Dirichlet line read 0 (they are filled from the end interpolant once the tile is in LDS).
 // FULL: the line length is a whole number of chunks, so on one-line tiles only the first and the
 // last group of NT elements can fall outside the line.
-template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL, class PA>
+// STREAM: strided tiles of whole lines read with streaming loads (no other tile of the pass reads
+// their operand again).
+template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL, class PA, bool STREAM = false>
 __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)], const PA &a, const T *v,
                                           const int64_t *lb, int64_t line0, int64_t cstart, int tid)
 {
+    auto ld = [](const T *p) { return STREAM ? ldg_stream(p) : ldg(p); };
     constexpr int H = ORDER / 2;
     constexpr int C = (NT / TC) * S;
     constexpr int W = C + 2 * H;
@@ -575,7 +587,7 @@ __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)]
         const int64_t step = (int64_t)(NT / TC) * a.stride;
 #pragma unroll
         for (int k = 0; k < FILL; ++k) {
-            vals[k] = (ok && tid + k * NT < TC * W) ? ldg(q) : T(0);
+            vals[k] = (ok && tid + k * NT < TC * W) ? ld(q) : T(0);
             q += step;
         }
     } else {
@@ -598,7 +610,7 @@ __device__ __forceinline__ void load_tile(T (&vals)[tile_fill(ORDER, S, TC, NT)]
             } else {
                 ok = ok && (p >= 0 && p < ni);
             }
-            vals[k] = ok ? ldg(v + lb[cc] + (int64_t)p * st) : T(0);
+            vals[k] = ok ? ld(v + lb[cc] + (int64_t)p * st) : T(0);
         }
     }
 }
