@@ -463,9 +463,10 @@ def host_info():
 def cpu_baseline(sc, torch, reps=10, warm=3):
     """The FP64 oracle on a bounded sample of the headline workload: the x, y and z passes of one
     heat step (u <- u - D_0 u along one axis, order 6, Dirichlet, alpha = 1/sqrt(dx), dx = 1/511),
-    each over 128 full lines of 512 points (the per-line work of the 512^3 step).  Two builds --
-    the reference build every test checks (-O2 -ffp-contract=off) and a labelled -O3 -march=native
-    timing build -- on one thread and on all threads the process may use; `warm` untimed runs,
+    each over 512 full lines of 512 points (a plane of the 512^3 step; about 15 s of CPU work in
+    all).  Two builds -- the reference build every test checks (-O2 -ffp-contract=off) and a
+    labelled -O3 -march=native timing build -- on one thread and on all threads the process may
+    use; `warm` untimed runs,
     then `reps` timed runs, minimum and median.  The GPU applies the same passes to the same sample
     arrays and its error against the oracle is reported."""
     import numpy as np
@@ -473,16 +474,16 @@ def cpu_baseline(sc, torch, reps=10, warm=3):
     import oracle
     from paper_2007_03041_amd import workloads as W
 
-    n, lines = HEAT_N, 128
+    n, lines = HEAT_N, 512
     dx = 1.0 / (n - 1)
     alpha = 1.0 / math.sqrt(dx)
-    # x lines: grid (512, 128); y/z lines: grid (128, 512) along its second axis (strided lines)
+    # x lines: grid (512, lines); y/z lines: grid (lines, 512) along its second axis (strided lines)
     gx = oracle.make_grid((n, lines), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet"))
     gy = oracle.make_grid((lines, n), (0.0, 0.0), (1.0, 1.0), ("dirichlet", "dirichlet"))
     full = W.bump_field(n, device="cuda")                       # the headline's initial data
-    vx = full[n // 2, n // 2 - lines // 2:n // 2 + lines // 2, :].cpu().numpy().copy()  # 128 x lines
-    vy = full[n // 2, :, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # 128 y lines
-    vz = full[:, n // 2, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # 128 z lines
+    vx = full[n // 2, n // 2 - lines // 2:n // 2 + lines // 2, :].cpu().numpy().copy()  # x lines
+    vy = full[n // 2, :, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # y lines
+    vz = full[:, n // 2, n // 2 - lines // 2:n // 2 + lines // 2].cpu().numpy().copy()  # z lines
     del full
     cases = ((gx, 0, vx), (gy, 1, vy), (gy, 1, vz))
     sample_dof_apps = 3 * n * lines
