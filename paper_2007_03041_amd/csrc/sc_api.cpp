@@ -284,7 +284,7 @@ int spin_limit()
 // One pass along `dim`: out = acc_term + sum_ops scale * result(op).
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v,
                    const void *acc, int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes,
-                   hipStream_t st, int64_t nn_cpb)
+                   hipStream_t st, int64_t nn_cpb, double vw, double aw)
 {
     const Axis ax = axis_of(g, dim);
     const int elem = (int)elem_bytes(g);
@@ -303,6 +303,8 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     a.nchunks = (ax.n + C - 1) / C;
     a.bc = ax.bc;
     a.acc_mode = acc_mode;
+    a.vw = vw;
+    a.aw = aw;
     a.nops = nops;
     fill_ext(&a, order);
     bool multi = false;
@@ -318,7 +320,7 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
         }
     }
     if (nn_cpb > 0 && (multi || nn_cpb > INT32_MAX)) return fail(SC_ERR_ARG, "internal: bad nearest-neighbour block");
-    if (multi && (nops != 1 || a.nchunks != 1 || ax.bc != SC_BC_PERIODIC || acc_mode != 0))
+    if (multi && (nops != 1 || a.nchunks != 1 || ax.bc != SC_BC_PERIODIC))
         return fail(SC_ERR_UNSUPPORTED, "internal: fused powers of D need one periodic operator on whole lines");
     const int64_t tiles = (ax.nlines + scx::variant(vid).TC - 1) / scx::variant(vid).TC;
     if (tiles * a.nchunks > (int64_t)INT32_MAX) return fail(SC_ERR_SHAPE, "too many lines for one launch");
@@ -329,14 +331,14 @@ sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int 
     hipError_t e;
     if (a.nchunks == 1) {
         // Strided lines of exactly one tile whose tiles are adjacent, aligned lines: the pipelined
-        // persistent form, where it measured faster (512^3, per pass): FP32 always (0.40 -> 0.35
-        // ms: its arithmetic is the longer part and now overlaps the loads), FP64 with one operator
-        // on lines strided by 1 MiB or more (z: 0.57 -> 0.55 ms; y, 4 KiB apart, 0.47 -> 0.48 ms;
-        // with two operators the pipelined FP64 kernel spills).  SC_PIPE overrides (pipe_mode).
+        // persistent form, where it measured faster (512^3, per pass): FP32 (0.40 -> 0.35 ms: its
+        // arithmetic is the longer part and overlaps the loads there).  FP64 passes, whose plain
+        // form streams its strided loads and stores, run z in 0.52 ms against 0.54 pipelined.
+        // SC_PIPE overrides (pipe_mode).
         const scx::Variant &V = scx::variant(vid);
         const bool pipe = !V.contig && !multi && scx::pipe_variant(vid, elem) && ax.n == V.C() && ax.nlines % V.TC == 0 &&
                           ax.stride % V.TC == 0 && ((uintptr_t)v & 15) == 0 && pipe_mode() != 0 &&
-                          (pipe_mode() == 1 || elem == 4 || (nops == 1 && ax.stride * elem >= (int64_t(1) << 20)));
+                          (pipe_mode() == 1 || elem == 4);
         e = timed(kFused[dim], st, [&](const char **) {
             return pipe ? scx::launch_line_pass_pipe(a, elem, order, vid, st)
                         : scx::launch_line_pass(a, elem, order, vid, scx::LMODE_FUSED, multi, st);
@@ -671,38 +673,62 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
         }
     }
     if (stages > 1) {
-        // s-stage SSP Runge-Kutta with every D replaced by S_s (Sec. 2.5); E(v) = v + sum scale S_s[v]
+        // s-stage SSP Runge-Kutta with every D replaced by S_s (Sec. 2.5): each stage is
+        // out = ca acc + cb E(v), E(v) = v + sum over axes and operators of scale S_s[v].  The
+        // partial-sum passes form it themselves: the first one adds cb v (and ca acc) to its
+        // cb scale S_s[v], each later one adds its own term onto out.  Lines longer than one tile
+        // take their powers of D pass by pass into a scratch field, combined afterwards.
         const int elem = (int)elem_bytes(grid);
         const int64_t nel = ax0.total;
         char *U1 = wsp, *B = wsp + round256(fbytes), *TMP = B + round256(fbytes);
         char *psw = TMP + round256(fbytes);
         const size_t psw_bytes = ws_bytes - 3 * round256(fbytes);
-        auto lin = [&](double a, const void *x, double b, const void *y, void *o) {
-            return timed("lincomb", st, [&](const char **) { return scx::launch_lincomb(nel, elem, a, x, b, y, o, st); });
+        auto lin = [&](double a, const void *x, double b, const void *y, void *o) -> sc_status {
+            const hipError_t e = timed("lincomb", st, [&](const char **) {
+                return scx::launch_lincomb(nel, elem, a, x, b, y, o, st);
+            });
+            return e == hipSuccess ? SC_OK : fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
         };
-        auto euler = [&](const void *v, void *o) -> sc_status {
-            if (lin(1.0, v, 0.0, v, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+        // out = ca acc + cb E(v); acc is read only when ca != 0 and may be out; v is not out
+        auto stage = [&](const void *v, double ca, const void *acc, double cb, void *out) -> sc_status {
+            bool first = true;
             for (int d = 0; d < grid->ndim; ++d)
                 for (int k = 0; k < nops[d]; ++k) {
-                    sc_status r = sc_apply_D_partial_sum(grid, d, ops[d][k].op, pde->order, ops[d][k].alpha, stages,
-                                                         ops[d][k].scale, nullptr, v, TMP, psw, psw_bytes, stream);
+                    const OpSpec &op = ops[d][k];
+                    sc_status r;
+                    if (nchunks_for(axis_of(grid, d), elem) == 1) {
+                        const OpSpec o{op.op, op.alpha, cb * op.scale, stages};
+                        r = first ? run_pass(grid, d, pde->order, &o, 1, v, acc, ca != 0.0 ? 3 : 1, out, nullptr, psw,
+                                             psw_bytes, st, 0, cb, ca)
+                                  : run_pass(grid, d, pde->order, &o, 1, v, out, 2, out, nullptr, psw, psw_bytes, st);
+                    } else {
+                        r = sc_apply_D_partial_sum(grid, d, op.op, pde->order, op.alpha, stages, cb * op.scale, nullptr,
+                                                   v, TMP, psw, psw_bytes, stream);
+                        if (r == SC_OK) {
+                            if (!first)
+                                r = lin(1.0, out, 1.0, TMP, out);
+                            else if (ca == 0.0)
+                                r = lin(cb, v, 1.0, TMP, out);
+                            else if ((r = lin(cb, v, 1.0, TMP, TMP)) == SC_OK)
+                                r = lin(ca, acc, 1.0, TMP, out);
+                        }
+                    }
                     if (r != SC_OK) return r;
-                    if (lin(1.0, o, 1.0, TMP, o) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
+                    first = false;
                 }
+            if (first) return ca == 0.0 ? lin(cb, v, 0.0, v, out) : lin(ca, acc, cb, v, out);  // no operators
             return SC_OK;
         };
         for (int step = 0; step < nsteps; ++step) {
-            s = euler(u, U1);
-            if (s == SC_OK) s = euler(U1, B);
+            s = stage(u, 0.0, nullptr, 1.0, U1);
             if (s != SC_OK) return s;
             if (stages == 2) {
-                if (lin(0.5, u, 0.5, B, u) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
-                continue;
+                s = stage(U1, 0.5, u, 0.5, u);
+            } else {
+                s = stage(U1, 0.75, u, 0.25, B);
+                if (s == SC_OK) s = stage(B, 1.0 / 3.0, u, 2.0 / 3.0, u);
             }
-            if (lin(0.75, u, 0.25, B, U1) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
-            s = euler(U1, B);
             if (s != SC_OK) return s;
-            if (lin(1.0 / 3.0, u, 2.0 / 3.0, B, u) != hipSuccess) return fail(SC_ERR_DEVICE, "launch failed");
         }
         return SC_OK;
     }

@@ -47,7 +47,7 @@ struct OpArgs {
 
 struct PassArgs {
     const void *v;          // operand
-    const void *acc;        // acc_mode 2: added to the result (may equal out)
+    const void *acc;        // acc_mode bit 1: aw acc added to the result (may equal out)
     void *out;
     const double *g;        // Dirichlet values, 2 per line, or nullptr (= 0)
     double *agg;            // chunked: per (op, line, chunk) [fwd total, bwd total, J_R[0]]
@@ -59,7 +59,7 @@ struct PassArgs {
     int64_t ncells;         // n (periodic) or n - 1 (Dirichlet)
     int64_t nchunks;
     int32_t bc;             // 0 periodic, 1 Dirichlet
-    int32_t acc_mode;       // 0 none, 1 add the operand v, 2 add acc
+    int32_t acc_mode;       // bit 0: add vw v (the operand); bit 1: add aw acc
     int32_t nops;           // 1 or 2
     int32_t fuse_carry;     // chunked apply: each tile forms its chunk carries from the aggregates
     uint32_t *sync;         // single-pass chunked launches: the tile claim counter
@@ -69,6 +69,7 @@ struct PassArgs {
     int32_t win_k;          // > 0: windowed apply of chunked one-line tiles: the carries are the
                             // sweeps over the win_k points before and after the chunk
     int32_t pad_;
+    double vw, aw;          // weights of the operand and of acc in the result (acc_mode)
     // Dirichlet ends: the one-sided stencils of the order/2 points nearest an end integrate the
     // interpolant through the `order` end values; extending the line by that interpolant's values
     // at m = 1..order/2 points beyond the end makes the centred interior stencil integrate the same

@@ -92,7 +92,7 @@ int64_t nchunks_for(const Axis &ax, int elem);
 // nn_cpb > 0: nearest-neighbour virtual blocks of nn_cpb chunks (the line's mu terms dropped)
 sc_status run_pass(const sc_grid *g, int dim, int order, const OpSpec *ops, int nops, const void *v, const void *acc,
                    int acc_mode, void *out, const double *dg, char *wsp, size_t ws_bytes, hipStream_t st,
-                   int64_t nn_cpb = 0);
+                   int64_t nn_cpb = 0, double vw = 1.0, double aw = 1.0);
 int64_t chunk_points(const Axis &ax, int elem);
 // K of the windowed chunk carries for this pass and tile shape, or 0 (exact carries)
 int window_k(const PassArgs &a, int order, const Variant &V, bool multi);

@@ -64,6 +64,22 @@ def test_config1_replicated_lines(gpu_lib):
         assert err(got, ref, 1024.0 ** 2 * np.abs(v).max()) < TOL
 
 
+@pytest.mark.parametrize("k", [5, 8])
+@pytest.mark.parametrize("dim", [0, 1])
+def test_fused_high_powers_of_D(gpu_lib, k, dim):
+    """S_k = D + ... + D^k fused in one pass for k up to 8 (whole periodic lines along x and y, each
+    power's operand exchanged through the tile), every operator, against the oracle's powers."""
+    sc = gpu_lib
+    n = (256, 200)
+    v = W.random_field((n[1], n[0]), index=40 + k + dim)
+    g = Grid(n, (0.0, 0.0), (1.0, 0.8))
+    alpha = 0.6 / g.dx(dim)
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), dim, op, 6, alpha, k, -0.4, v)
+        got = host(sc.apply_D_partial_sum(dev(v), g, dim, op, 6, alpha, k, -0.4))
+        assert err(got, ref, max(np.abs(ref).max(), np.abs(v).max())) < TOL, op
+
+
 # ------------------------------------------------------------------------------ ragged 1-D lines
 CASES = []
 _r = np.random.default_rng(5)

@@ -28,6 +28,23 @@ def test_rk_matches_oracle(gpu_lib, stages, n):
     assert np.abs(u.cpu().numpy() - ref).max() < 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("stages", [2, 3])
+@pytest.mark.parametrize("n", [(24, 20, 36), (16, 12, 520)])
+def test_rk_3d_matches_oracle(gpu_lib, stages, n):
+    """Three periodic axes, two operators on each (every stage's passes after the first accumulate
+    onto its result; y and z through strided tiles, z lines of 520 points chunked)."""
+    u0 = W.random_field(tuple(reversed(n)), index=70 + stages)
+    g = Grid(n, (0.0,) * 3, tuple(2 * np.pi * m / n[0] for m in n))
+    dt = 0.02
+    c, nu_diff = (1.0, -0.7, 0.4), 0.05
+    beta = 0.5
+    ref = oracle.time_step_rk(oracle.make_grid(g.n, g.lo, g.hi, g.bc), c, nu_diff, beta, dt, 6, 2, u0, stages)
+    u = torch.from_numpy(u0.copy()).cuda()
+    sc.time_step(u, g, 2, c=c, nu_diff=nu_diff, beta=beta, dt=dt, order=6, stages=stages)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - ref).max() < 1e-11 * np.abs(ref).max()
+
+
 def test_rk3_mixed_path(gpu_lib):
     import dataclasses
 
