@@ -17,11 +17,12 @@ from the committed rocprofv3 counter summaries when they were taken on the curre
 ``cpu_baseline`` times the FP64 oracle on a bounded sample of the same workload on the host cores.
 ``beside`` holds the other workloads measured the same way: the same heat step on the mixed
 FP32/FP64 path, the 2-D advection-diffusion step (4096^2), the 1-D line workload replicated to
-2^18 lines, the ragged batch, the Hamilton-Jacobi solver with classical and learned weights, a
-plain device copy, and the nearest-neighbour block form of Sec. 3 beside the exact carries.
+2^18 lines, the Runge-Kutta steps with partial sums (256^3), the ragged batch, the Hamilton-Jacobi
+solver with classical and learned weights, a plain device copy, and the nearest-neighbour block form
+of Sec. 3 beside the exact carries.
 
 ``--only LEG`` runs one leg (for profiling): heat3d_f64, heat3d_mixed, advdiff2d, line1d, batch, hj,
-copy, nn.
+copy, nn, rk.
 """
 from __future__ import annotations
 
@@ -44,6 +45,7 @@ METRIC = "DOF updates/s per L^{-1}/D application on 1 GPU; % HBM roofline; error
 HEAT_N = 512
 ADV_N = 4096
 LINE_N, LINE_LINES = 1024, 1 << 18
+RK_N = 256
 NFIELDS = 4  # 2-D leg: rotate independent fields (134 MB each) so a pass never re-reads from cache
 
 
@@ -269,6 +271,32 @@ def nn_leg(sc, torch, steps, warmup, n=ADV_N):
     exact = sc.apply_invL(v, g, 1, "R", 6, alpha)
     nn = sc.apply_invL_nn(v, g, 1, "R", 6, alpha, block)
     res["max_rel_diff_nn_vs_exact"] = ((nn - exact).abs().max() / exact.abs().max()).item()
+    return res
+
+
+def rk_leg(sc, torch, steps, warmup, n=RK_N):
+    """3-D linear advection-diffusion u_t + c.grad u = nu lap u, 256^3 periodic on [0, 2 pi]^3,
+    order 6, c = (1, 0.5, 0.25), nu = 0.01, beta = 0.35, dt = 1e-3, unsplit: one step of forward
+    Euler with D (s = 1) and of the s-stage Runge-Kutta forms with the partial sums S_s (s = 2, 3;
+    Sec. 2.5), FP64 and mixed.  Each stage is its partial-sum passes alone (two operators on each of
+    three axes); the stage combinations ride in their epilogues."""
+    from paper_2007_03041_amd import workloads as W
+
+    res = {"workload": f"3-D advection-diffusion {n}^3 periodic, order 6, c=(1, 0.5, 0.25), nu=0.01, beta=0.35, "
+                       "dt=1e-3, unsplit; forward Euler (s=1) and SSP Runge-Kutta with S_s (s=2, 3)"}
+    u0 = torch.from_numpy(W.random_field((n, n, n), index=90)).to("cuda")
+    for dname, dtype, tdt in (("f64", sc.SC_F64, torch.float64), ("mixed", sc.SC_F32_MIXED, torch.float32)):
+        g = sc.Grid((n,) * 3, (0.0,) * 3, (2 * math.pi,) * 3, dtype=dtype)
+        for s in (1, 2, 3):
+            u = u0.to(tdt)
+            st = sc.TimeStepper(g, sc.make_pde(c=(1.0, 0.5, 0.25), nu_diff=0.01, beta=0.35, dt=1e-3, order=6,
+                                               stages=s))
+            m = measure(sc, torch, lambda: st.step(u, 1), steps, warmup)
+            res[f"{dname}_s{s}"] = {"ms_min": m["step_ms_min"], "ms_median": m["step_ms_median"],
+                                    "dof_steps_per_s": n ** 3 / (m["step_ms_median"] / 1e3),
+                                    "launches_per_step": sum(m["kernel_launches_per_step"].values()),
+                                    "kernel_ms": m["kernel_ms"]}
+            del u, st
     return res
 
 
@@ -613,7 +641,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no beside legs)")
     ap.add_argument("--only", choices=("heat3d_f64", "heat3d_mixed", "advdiff2d", "line1d", "batch", "hj", "copy",
-                                       "nn"))
+                                       "nn", "rk"))
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--ingest-counters", nargs="+", metavar="WORKLOAD=DIR",
                     help="write profiles/traffic_counters.json from rocprofv3 --pmc runs (no GPU needed)")
@@ -649,6 +677,8 @@ def main():
             rec = hj_legs(sc, torch)
         elif args.only == "nn":
             rec = nn_leg(sc, torch, args.steps, args.warmup)
+        elif args.only == "rk":
+            rec = rk_leg(sc, torch, args.steps, args.warmup)
         else:
             rec = copy_leg(torch)
         print(json.dumps({"only": args.only, **rec}), flush=True)
@@ -723,6 +753,8 @@ def main():
         beside["advdiff2d_4096"] = advdiff2d(sc, torch, args.steps, args.warmup)
         torch.cuda.empty_cache()
         beside["line1d_replicated"] = line1d(sc, torch, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        beside["runge_kutta_256"] = rk_leg(sc, torch, args.steps, args.warmup)
         torch.cuda.empty_cache()
         beside["device_copy_1GiB"] = copy_leg(torch)
         torch.cuda.empty_cache()
