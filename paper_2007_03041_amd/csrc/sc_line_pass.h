@@ -657,12 +657,11 @@ __device__ __forceinline__ int64_t xcd_grouped(int64_t b, int64_t nblocks)
 }
 
 // Single-power passes are held to 128 VGPRs (4 waves per SIMD): left alone, the compiler gave the
-// one-operator x passes 129-131 and so one workgroup per CU less.  The fused powers of D (about 190
-// registers in FP64) are held to 168 (3 waves) along x, where that measured faster despite some
-// spilling (512^3 S_3: 1.42 -> 1.22 ms), and keep their registers along y/z, where the spilling
-// form was slower (1.71 -> 2.24 ms).
+// one-operator x passes 129-131 and so one workgroup per CU less.  The fused powers of D keep their
+// registers (about 190-230 in FP64, 2 waves): held to 168 they spill, and measured slower along
+// every axis (512^3 FP64 S_3: x 0.85 -> 0.96, y 1.08 -> 1.16, z 1.20 -> 1.31 ms).
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int MODE, int NT, int NOPS, bool MULTI, bool FULL>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MULTI ? (CONTIG ? 3 : 1) : 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MULTI ? 1 : 4)))
 line_pass(const PassArgs a)
 {
     constexpr bool PIPE = false;

@@ -45,6 +45,17 @@ def test_rk_3d_matches_oracle(gpu_lib, stages, n):
     assert np.abs(u.cpu().numpy() - ref).max() < 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("stages", [2, 3])
+def test_rk_without_operators_keeps_the_field(gpu_lib, stages):
+    """No advection and no diffusion: every stage is E(v) = v, formed by element-wise combinations
+    alone; the field stays what it was (to the rounding of the stage weights)."""
+    u0 = W.random_field((40, 64), index=80 + stages)
+    u = torch.from_numpy(u0.copy()).cuda()
+    sc.time_step(u, Grid((64, 40)), 2, c=(0.0, 0.0), nu_diff=0.0, beta=0.5, dt=0.1, order=6, stages=stages)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - u0).max() <= 1e-15 * np.abs(u0).max()
+
+
 def test_rk3_mixed_path(gpu_lib):
     import dataclasses
 
