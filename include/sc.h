@@ -185,11 +185,13 @@ double sc_effective_dt(const sc_grid *grid, const sc_linear_pde *pde);
 const char *sc_last_error(void);
 
 /* ------------------------------------------------------------------------------------------------
- * Batches of independent instances.  Instance i is nlines lines of n contiguous points at element
- * offset `offset` of the batch arrays v and out (the same offset in both; dtype of the plan), each
- * line on [lo, hi] with the grid convention of sc_grid, its own alpha, boundary and operator.  The
- * plan applies, along every instance's lines, L_op^{-1} (k = 0) or scale * D (k = 1) -- the
- * operations of sc_apply_invL / sc_apply_D_partial_sum -- in one launch per tile shape.
+ * Batches of independent instances.  Instance i is nlines lines of n points at element offset
+ * `offset` of the batch arrays v and out (the same offset in both; dtype of the plan): axis 0, the
+ * points of line l are contiguous (point p at offset + l n + p: x lines); axis 1, the lines are
+ * interleaved (point p at offset + p nlines + l: the y lines of an array of n rows of nlines points).
+ * Each line is on [lo, hi] with the grid convention of sc_grid, with its instance's alpha, boundary
+ * and operator.  The plan applies, along every instance's lines, L_op^{-1} (k = 0) or scale * D
+ * (k = 1) -- the operations of sc_apply_invL / sc_apply_D_partial_sum -- in one launch per tile shape.
  * ---------------------------------------------------------------------------------------------- */
 typedef struct {
     int64_t offset;   /* element offset of the instance's first point in v and out */
@@ -202,13 +204,13 @@ typedef struct {
     int32_t bc;       /* sc_bc */
     int32_t op;       /* sc_op */
     int32_t k;        /* 0 or 1 */
-    int32_t reserved; /* 0 */
+    int32_t axis;     /* 0: contiguous lines; 1: interleaved lines (see above) */
 } sc_batch_item;
 
 typedef struct sc_batch_plan_s *sc_batch_plan;
 
 /* Validates the instances (copied) and prepares the launches with the tile shapes the autotuner
- * chose earlier in this process for instances of the same class (line length rounded up to a
+ * chose earlier in this process for instances of the same class (axis; line length rounded up to a
  * power of two; single- or multi-line), default shapes otherwise.  Allocates the plan's device
  * tables (hipMalloc) on the current device and a private capture stream.  dtype: sc_dtype. */
 sc_status sc_batch_plan_create(const sc_batch_item *items, int count, int dtype, int order, sc_batch_plan *plan);
@@ -225,9 +227,9 @@ sc_status sc_batch_apply(sc_batch_plan plan, const void *v, void *out, const dou
 /* The same results through one sc_apply_invL / sc_apply_D_partial_sum call per instance. */
 sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws,
                                       size_t ws_bytes, sc_stream_t stream);
-/* Autotuner: times every candidate tile shape (chunk length and lines per tile of the x-line
- * variants; persistent or one workgroup per work item; windowed or exact chunk carries where the
- * windowed ones apply) on each class of the plan's instances, `reps` runs each, on the caller's
+/* Autotuner: times every candidate tile shape (chunk length and lines per tile of the variants of
+ * the class's axis: x-line tiles, or strided tiles of 16 or 32 lines; persistent or one workgroup
+ * per work item; windowed or exact chunk carries where the windowed ones apply) on each class of the plan's instances, `reps` runs each, on the caller's
  * arrays (out is overwritten), keeps the fastest per class for this plan and for plans created
  * later in the process (sc_batch_tune_export saves the table).
  * Synchronises `stream`; needs ws_bytes >= sc_batch_workspace_bytes(plan). */
@@ -236,8 +238,9 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
 /* JSON description of the plan's launches and tile shapes; returns its length (buf may be NULL). */
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len);
 /* The autotuner's table of this process as text, one class a line: "elem order nbits multi variant
- * persistent exact" (elem 8 or 4 bytes; nbits = ceil(log2 n); multi = nlines >= 4; exact = 1: exact
- * chunk carries where the windowed ones would apply).  Returns its length; writes at most len - 1
+ * persistent exact axis" (elem 8 or 4 bytes; nbits = ceil(log2 n); multi = nlines >= 4; exact = 1:
+ * exact chunk carries where the windowed ones would apply; axis of the instances; import also takes
+ * lines without the axis, as axis 0).  Returns its length; writes at most len - 1
  * characters and a terminating 0 to buf (buf may be NULL). */
 int sc_batch_tune_export(char *buf, int len);
 /* Merges such a table (e.g. saved from an earlier process) into this process's; plans created

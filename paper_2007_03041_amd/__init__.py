@@ -61,7 +61,7 @@ class sc_linear_pde(ctypes.Structure):
 class sc_batch_item(ctypes.Structure):
     _fields_ = [("offset", c_int64), ("n", c_int64), ("nlines", c_int64), ("lo", c_double), ("hi", c_double),
                 ("alpha", c_double), ("scale", c_double), ("g_offset", c_int64), ("bc", c_int32),
-                ("op", c_int32), ("k", c_int32), ("reserved", c_int32)]
+                ("op", c_int32), ("k", c_int32), ("axis", c_int32)]
 
 
 class sc_hj_params(ctypes.Structure):
@@ -431,8 +431,9 @@ class BatchPlan:
     """A plan over many independent instances (``sc_batch_*``).
 
     ``items``: sequence of dicts with keys offset, n, nlines, lo, hi, alpha, bc ("periodic" or
-    "dirichlet"), op ("L", "R", "0"), k (0 or 1), and optionally scale (default 1) and g_offset
-    (default -1).  Arrays are flat contiguous device tensors of the plan's dtype (float64 for
+    "dirichlet"), op ("L", "R", "0"), k (0 or 1), and optionally scale (default 1), g_offset
+    (default -1) and axis (default 0: contiguous lines; 1: interleaved lines, point p of line l at
+    offset + p * nlines + l).  Arrays are flat contiguous device tensors of the plan's dtype (float64 for
     SC_F64, float32 for SC_F32_MIXED) with at least ``elements`` entries.
     """
 
@@ -445,7 +446,7 @@ class BatchPlan:
             e.lo, e.hi, e.alpha = float(it["lo"]), float(it["hi"]), float(it["alpha"])
             e.scale = float(it.get("scale", 1.0))
             e.g_offset = int(it.get("g_offset", -1))
-            e.bc, e.op, e.k, e.reserved = BCS[it["bc"]], OPS[it["op"]], int(it["k"]), 0
+            e.bc, e.op, e.k, e.axis = BCS[it["bc"]], OPS[it["op"]], int(it["k"]), int(it.get("axis", 0))
         self._h = c_void_p()
         _check(lib.sc_batch_plan_create(arr, len(items), dtype, order, ctypes.byref(self._h)))
         self.dtype, self.order, self.count = dtype, order, len(items)

@@ -1,11 +1,13 @@
-// sc_batch.cpp -- batched application over many independent instances: the x lines of every
-// instance (own length, line count, alpha, boundary, operator) in one pass per tile shape.
+// sc_batch.cpp -- batched application over many independent instances: the lines of every
+// instance (own length, line count, alpha, boundary, operator; contiguous or interleaved lines) in
+// one pass per tile shape.
 //
 // A plan groups the instances by the tile shape chosen for them; each group is one launch of the
 // persistent batched line pass over a work list of (instance, tile) items (chunked groups: an
 // aggregate launch, a carry launch and an apply launch).  Shapes come from an autotuner that times
-// every x-line variant, persistent or one workgroup per item, per class of instances (line length
-// rounded up to a power of two, single- or multi-line), and remembers the winners for the process.
+// every variant of the instances' layout, persistent or one workgroup per item, per class of
+// instances (layout, line length rounded up to a power of two, single- or multi-line), and remembers
+// the winners for the process.
 // The launches of a plan can be captured once into a HIP graph and replayed as one launch.
 #include "sc.h"
 
@@ -31,8 +33,16 @@ using namespace scx::host;
 
 namespace {
 
-// x-line variants a batch may use (see SC_VARIANTS)
+// variants a batch may use (see SC_VARIANTS): contiguous lines (axis 0) take the x-line tiles,
+// interleaved lines (axis 1) the strided 16- and 32-line tiles
 const int kBatchVariants[] = {14, 0, 10, 1, 16, 9, 2, 3, 15};
+const int kBatchStridedVariants[] = {4, 5, 6, 11, 12};
+
+std::vector<int> batch_variants(int axis)
+{
+    return axis == 0 ? std::vector<int>(std::begin(kBatchVariants), std::end(kBatchVariants))
+                     : std::vector<int>(std::begin(kBatchStridedVariants), std::end(kBatchStridedVariants));
+}
 
 struct Choice {
     int vid = -1;
@@ -41,10 +51,10 @@ struct Choice {
 };
 
 struct ClassKey {
-    int elem, order, nbits, multi;
+    int elem, order, nbits, multi, axis;
     bool operator<(const ClassKey &o) const
     {
-        return std::tie(elem, order, nbits, multi) < std::tie(o.elem, o.order, o.nbits, o.multi);
+        return std::tie(axis, elem, order, nbits, multi) < std::tie(o.axis, o.elem, o.order, o.nbits, o.multi);
     }
 };
 
@@ -60,21 +70,30 @@ int ceil_log2(int64_t n)
 
 ClassKey class_of(const sc_batch_item &it, int elem, int order)
 {
-    return ClassKey{elem, order, ceil_log2(it.n), it.nlines >= 4 ? 1 : 0};
+    return ClassKey{elem, order, ceil_log2(it.n), it.nlines >= 4 ? 1 : 0, it.axis};
 }
 
 Choice default_choice(const sc_batch_item &it, int elem)
 {
     Choice c;
-    // SC_BATCH_VARIANT=<variant>[p]: every untuned instance takes that x-line variant (p: persistent)
+    // SC_BATCH_VARIANT=<variant>[p]: every untuned instance of that variant's layout takes it
+    // (p: persistent)
     if (const char *env = std::getenv("SC_BATCH_VARIANT")) {
         const int vid = std::atoi(env);
-        for (int v : kBatchVariants)
+        for (int v : batch_variants(it.axis))
             if (v == vid && variant_built(vid, elem)) {
                 c.vid = vid;
                 c.persistent = std::strchr(env, 'p') ? 1 : 0;
                 return c;
             }
+    }
+    if (it.axis == 1) {
+        // the tiles of single y/z passes (a strided shape the batch is not built for: 16 x 512)
+        const int vid = pick_variant(false, it.n, elem);
+        bool ok = false;
+        for (int v : kBatchStridedVariants) ok = ok || v == vid;
+        c.vid = ok ? vid : 5;
+        return c;
     }
     if (it.nlines >= 4) {
         c.vid = it.n <= 256 ? 0 : it.n <= 512 ? 10 : it.n <= 1024 ? 1 : it.n <= 2048 ? 16 : it.n <= 4096 ? 2 : 3;
@@ -89,7 +108,7 @@ Axis item_axis(const sc_batch_item &it)
 {
     Axis ax;
     ax.n = it.n;
-    ax.stride = 1;
+    ax.stride = it.axis == 1 ? it.nlines : 1;
     ax.nlines = it.nlines;
     ax.total = it.n * it.nlines;
     ax.bc = it.bc;
@@ -162,7 +181,7 @@ sc_status build(sc_batch_plan p)
         std::memset(&b, 0, sizeof(b));
         PassArgs &a = b.a;
         a.n = it.n;
-        a.stride = 1;
+        a.stride = ax.stride;
         a.nlines = it.nlines;
         a.ncells = ax.ncells;
         a.nchunks = (it.n + V.C() - 1) / V.C();
@@ -332,6 +351,7 @@ sc_status sc_batch_plan_create(const sc_batch_item *items, int count, int dtype,
         std::snprintf(where, sizeof(where), "instance %d: ", i);
         if (it.n < order + 1) return fail(SC_ERR_SHAPE, std::string(where) + "line shorter than the stencil");
         if (it.nlines < 1 || it.offset < 0) return fail(SC_ERR_SHAPE, std::string(where) + "bad line count or offset");
+        if (it.axis != 0 && it.axis != 1) return fail(SC_ERR_ARG, std::string(where) + "axis must be 0 or 1");
         if (it.n > (int64_t(1) << 40) / it.nlines) return fail(SC_ERR_SHAPE, std::string(where) + "too large");
         // tile index arithmetic along a line is 32-bit
         if (it.n > (int64_t(1) << 31) - 65536) return fail(SC_ERR_SHAPE, std::string(where) + "line longer than 2^31 - 2^16");
@@ -348,10 +368,10 @@ sc_status sc_batch_plan_create(const sc_batch_item *items, int count, int dtype,
         extent = std::max(extent, it.offset + it.n * it.nlines);
         if (it.g_offset >= 0) g_extent = std::max(g_extent, it.g_offset + 2 * it.nlines);
         size_t worst = 0;
-        for (int vid : kBatchVariants)
+        for (int vid : batch_variants(it.axis))
             if (variant_built(vid, elem)) worst = std::max(worst, item_chunk_doubles(it, variant(vid).C()));
         bound += worst * sizeof(double);
-        const int64_t C1 = variant(pick_variant(true, it.n, elem)).C();
+        const int64_t C1 = variant(pick_variant(it.axis == 0, it.n, elem)).C();
         per_max = std::max(per_max, chunk_ws_bytes(it.nlines, (it.n + C1 - 1) / C1, 1));
     }
     sc_batch_plan p = new sc_batch_plan_s;
@@ -451,24 +471,26 @@ sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *o
         const sc_batch_item &it = plan->items[i];
         sc_grid gr;
         std::memset(&gr, 0, sizeof(gr));
+        // the instance as a 2-D grid whose axis `d` holds its lines
+        const int d = it.axis;
         gr.ndim = 2;
-        gr.n[0] = it.n;
-        gr.n[1] = it.nlines;
+        gr.n[d] = it.n;
+        gr.n[1 - d] = it.nlines;
         gr.n[2] = 1;
-        gr.lo[0] = it.lo;
-        gr.hi[0] = it.hi;
-        gr.lo[1] = 0.0;
-        gr.hi[1] = 1.0;
-        gr.bc[0] = it.bc;
-        gr.bc[1] = SC_BC_PERIODIC;
+        gr.lo[d] = it.lo;
+        gr.hi[d] = it.hi;
+        gr.lo[1 - d] = 0.0;
+        gr.hi[1 - d] = 1.0;
+        gr.bc[d] = it.bc;
+        gr.bc[1 - d] = SC_BC_PERIODIC;
         gr.dtype = plan->dtype;
         const char *vi = (const char *)v + (size_t)it.offset * plan->elem;
         char *oi = (char *)out + (size_t)it.offset * plan->elem;
         const double *gi = it.g_offset >= 0 ? g + it.g_offset : nullptr;
         if (it.k == 0)
-            s = sc_apply_invL(&gr, 0, it.op, plan->order, it.alpha, gi, vi, oi, ws, ws_bytes, stream);
+            s = sc_apply_invL(&gr, d, it.op, plan->order, it.alpha, gi, vi, oi, ws, ws_bytes, stream);
         else
-            s = sc_apply_D_partial_sum(&gr, 0, it.op, plan->order, it.alpha, 1, it.scale, gi, vi, oi, ws, ws_bytes,
+            s = sc_apply_D_partial_sum(&gr, d, it.op, plan->order, it.alpha, 1, it.scale, gi, vi, oi, ws, ws_bytes,
                                        stream);
         if (s != SC_OK) return s;
     }
@@ -502,7 +524,7 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
         sub.choice.resize(sub.items.size());
         float best = 1e30f;
         Choice best_c = plan->choice[kv.second[0]];
-        for (int vid : kBatchVariants) {
+        for (int vid : batch_variants(kv.first.axis)) {
             if (!variant_built(vid, plan->elem)) continue;
             for (int cand = 0; cand < 4; ++cand) {
                 const int pers = cand & 1, exact = cand >> 1;
@@ -514,7 +536,7 @@ sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const doub
                         PassArgs a;
                         std::memset(&a, 0, sizeof(a));
                         a.n = it.n;
-                        a.stride = 1;
+                        a.stride = item_axis(it).stride;
                         a.nlines = it.nlines;
                         a.nops = 1;
                         a.nchunks = (it.n + variant(vid).C() - 1) / variant(vid).C();
@@ -567,9 +589,10 @@ int sc_batch_tune_export(char *buf, int len)
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (auto &kv : g_tuned) {
-            char line[96];
-            std::snprintf(line, sizeof(line), "%d %d %d %d %d %d %d\n", kv.first.elem, kv.first.order, kv.first.nbits,
-                          kv.first.multi, kv.second.vid, kv.second.persistent, kv.second.exact);
+            char line[112];
+            std::snprintf(line, sizeof(line), "%d %d %d %d %d %d %d %d\n", kv.first.elem, kv.first.order,
+                          kv.first.nbits, kv.first.multi, kv.second.vid, kv.second.persistent, kv.second.exact,
+                          kv.first.axis);
             txt += line;
         }
     }
@@ -592,11 +615,15 @@ sc_status sc_batch_tune_import(const char *text)
         ClassKey k{};
         Choice c;
         char extra = 0;
-        if (std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %c", &k.elem, &k.order, &k.nbits, &k.multi, &c.vid,
-                        &c.persistent, &c.exact, &extra) != 7)
-            return fail(SC_ERR_ARG, "tune table line " + std::to_string(lineno) + ": expected 7 integers");
+        // (lines of seven integers, written before the layout field, are contiguous-line classes)
+        const int got_n = std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %d %c", &k.elem, &k.order, &k.nbits,
+                                      &k.multi, &c.vid, &c.persistent, &c.exact, &k.axis, &extra);
+        if (got_n != 7 && got_n != 8)
+            return fail(SC_ERR_ARG, "tune table line " + std::to_string(lineno) + ": expected 8 integers");
+        if (got_n == 7) k.axis = 0;
         bool known = false;
-        for (int v : kBatchVariants) known = known || v == c.vid;
+        if (k.axis == 0 || k.axis == 1)
+            for (int v : batch_variants(k.axis)) known = known || v == c.vid;
         if ((k.elem != 4 && k.elem != 8) || (k.order != 4 && k.order != 6) || k.nbits < 0 || k.nbits > 31 ||
             (k.multi != 0 && k.multi != 1) || !known || !variant_built(c.vid, k.elem) ||
             (c.persistent != 0 && c.persistent != 1) || (c.exact != 0 && c.exact != 1))
@@ -611,7 +638,7 @@ sc_status sc_batch_tune_import(const char *text)
 int sc_batch_describe(sc_batch_plan plan, char *buf, int len)
 {
     if (!plan) return -1;
-    std::map<std::tuple<int, int, int>, int> use;
+    std::map<std::tuple<int, int, int>, int> use;  // (the variant also tells the layout)
     for (const Choice &c : plan->choice) use[std::make_tuple(c.vid, c.persistent, c.exact)] += 1;
     std::string js = "{\"launches\": " + std::to_string(plan->launches.size()) + ", \"shapes\": [";
     bool first = true;
@@ -619,10 +646,10 @@ int sc_batch_describe(sc_batch_plan plan, char *buf, int len)
         const Variant &V = variant(std::get<0>(kv.first));
         char tmp[200];
         std::snprintf(tmp, sizeof(tmp),
-                      "%s{\"variant\": %d, \"S\": %d, \"TC\": %d, \"NT\": %d, \"chunk\": %d, \"persistent\": %d, "
-                      "\"exact_carries\": %d, \"instances\": %d}",
-                      first ? "" : ", ", std::get<0>(kv.first), V.S, V.TC, V.NT, V.C(), std::get<1>(kv.first),
-                      std::get<2>(kv.first), kv.second);
+                      "%s{\"variant\": %d, \"S\": %d, \"TC\": %d, \"NT\": %d, \"chunk\": %d, \"axis\": %d, "
+                      "\"persistent\": %d, \"exact_carries\": %d, \"instances\": %d}",
+                      first ? "" : ", ", std::get<0>(kv.first), V.S, V.TC, V.NT, V.C(), V.contig ? 0 : 1,
+                      std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
         js += tmp;
         first = false;
     }

@@ -310,7 +310,7 @@ hipError_t launch_line_pass_pipe(const PassArgs &a, int elem, int order, int vid
 
 hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int vid, hipStream_t st)
 {
-    if (!variant_built(vid, elem) || !variant(vid).contig) return hipErrorInvalidValue;
+    if (!variant_built(vid, elem) || !batch_built(variant(vid))) return hipErrorInvalidValue;
     if (b.nwork <= 0) return hipSuccess;
     if (elem == 8) {
         if (order == 4)
@@ -328,7 +328,7 @@ hipError_t launch_line_pass_batch(const BatchLaunch &b, int elem, int order, int
 
 int line_pass_batch_occupancy(int elem, int order, int vid, int mode, int full)
 {
-    if (!variant_built(vid, elem) || !variant(vid).contig) return 0;
+    if (!variant_built(vid, elem) || !batch_built(variant(vid))) return 0;
     if (elem == 8) {
         if (order == 4)
             return full ? line_pass_batch_occupancy_t<double, 4, true>(vid, mode)

@@ -867,11 +867,15 @@ hipError_t launch_line_pass_pipe_t(const PassArgs &a, int vid, hipStream_t st)
 // ------------------------------------------------------------------------------------------
 // Batched launches (contiguous variants only)
 // ------------------------------------------------------------------------------------------
+// Shapes the batched kernel is instantiated for: every x-line tile, and the strided tiles of 16 or 32
+// lines with S = 16 (the shapes of single y/z passes).
+constexpr bool batch_built(const Variant &V) { return V.contig || (V.S == 16 && (V.TC == 16 || V.TC == 32)); }
+
 template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL>
 static hipError_t launch_batch_shape(const BatchLaunch &b, hipStream_t st)
 {
     constexpr Variant V{S, TC, CONTIG, NT};
-    if constexpr (!CONTIG || V.lds_bytes((int)sizeof(T), ORDER, 2) > LDS_LIMIT) {
+    if constexpr (!batch_built(V) || V.lds_bytes((int)sizeof(T), ORDER, 2) > LDS_LIMIT) {
         return hipErrorInvalidValue;
     } else {
         const dim3 grid((unsigned)b.grid), block(NT);
@@ -900,7 +904,7 @@ template <typename T, int ORDER, int S, int TC, bool CONTIG, int NT, bool FULL>
 static int batch_occupancy_shape(int mode)
 {
     constexpr Variant V{S, TC, CONTIG, NT};
-    if constexpr (!CONTIG || V.lds_bytes((int)sizeof(T), ORDER, 2) > LDS_LIMIT) {
+    if constexpr (!batch_built(V) || V.lds_bytes((int)sizeof(T), ORDER, 2) > LDS_LIMIT) {
         return 0;
     } else {
         int occ = 0;

@@ -90,7 +90,7 @@ def test_batch_validation_before_device_use():
     base = dict(offset=0, n=100, nlines=1, lo=0.0, hi=1.0, alpha=50.0, scale=1.0, g_offset=-1, bc=0, op=2, k=0)
     cases = [(dict(n=6), sc.SC_ERR_SHAPE), (dict(k=2), sc.SC_ERR_UNSUPPORTED), (dict(alpha=0.0), sc.SC_ERR_ARG),
              (dict(bc=5), sc.SC_ERR_ARG), (dict(op=3), sc.SC_ERR_ARG), (dict(g_offset=0), sc.SC_ERR_ARG),
-             (dict(nlines=0), sc.SC_ERR_SHAPE), (dict(alpha=1e6), sc.SC_ERR_ARG)]
+             (dict(nlines=0), sc.SC_ERR_SHAPE), (dict(alpha=1e6), sc.SC_ERR_ARG), (dict(axis=2), sc.SC_ERR_ARG)]
     for bad, want in cases:
         arr = (sc.sc_batch_item * 1)()
         for k, v in dict(base, **bad).items():
@@ -189,14 +189,20 @@ def test_batch_tune_table_round_trip(tmp_path):
     with what the process held), and malformed or unbuilt entries are refused whole."""
     lib = sc.load()
     path = tmp_path / "tune.txt"
-    text = "8 6 14 1 14 1 0\n4 6 13 0 3 0 1\n"
+    text = "8 6 14 1 14 1 0 0\n4 6 13 0 3 0 1 0\n8 6 9 1 5 1 0 1\n4 4 8 1 12 0 0 1\n"
     path.write_text(text)
     sc.batch_tune_load(str(path))
     out = tmp_path / "out.txt"
     sc.batch_tune_save(str(out))
     lines = set(out.read_text().splitlines())
     assert set(text.splitlines()) <= lines
-    for bad in ("8 6 14 1 14 1\n", "8 6 14 1 99 0 0\n", "8 5 14 1 14 0 0\n", "8 6 14 1 14 0 0 7\n"):
+    # a line without the axis field is a class of contiguous lines
+    assert lib.sc_batch_tune_import(b"8 4 12 0 16 0 0\n") == sc.SC_OK
+    sc.batch_tune_save(str(out))
+    lines = set(out.read_text().splitlines())
+    assert "8 4 12 0 16 0 0 0" in lines
+    for bad in ("8 6 14 1 14 1\n", "8 6 14 1 99 0 0 0\n", "8 5 14 1 14 0 0 0\n", "8 6 14 1 14 0 0 7\n",
+                "8 6 14 1 14 0 0 1\n", "8 6 14 1 5 0 0 0\n", "8 6 14 1 14 0 0 0 0\n"):
         assert lib.sc_batch_tune_import(bad.encode()) == sc.SC_ERR_ARG, bad
     # a refused text changes nothing
     sc.batch_tune_save(str(out))

@@ -1,7 +1,8 @@
 """GPU parity of batched application (sc_batch_*): many independent instances of uneven length,
-line count, alpha, boundary and operator in one launch per tile shape, against the FP64 oracle
-instance by instance (FP64 1e-12, mixed 1e-5, normalised as in the other parity tests), through
-the plain, graph-replayed, tuned and one-launch-per-instance paths."""
+line count, alpha, boundary, operator and layout (contiguous or interleaved lines) in one launch
+per tile shape, against the FP64 oracle instance by instance (FP64 1e-12, mixed 1e-5, normalised as
+in the other parity tests), through the plain, graph-replayed, tuned and one-launch-per-instance
+paths."""
 import math
 
 import numpy as np
@@ -15,14 +16,15 @@ from paper_2007_03041_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def small_batch(count=48, seed=7):
-    """Ragged instances covering every tile shape: n from 7 to 20000 (log-uniform), 1 to 17 lines,
-    nu from 1e-3 to 20, both boundaries, all operators, k = 0 / 1, Dirichlet values on some."""
+def small_batch(count=48, seed=7, interleaved=0.0, nmax=20000, lines=(1, 1, 2, 3, 5, 17)):
+    """Ragged instances covering every tile shape: n from 7 to nmax (log-uniform), line counts from
+    `lines`, nu from 1e-3 to 20, both boundaries, all operators, k = 0 / 1, Dirichlet values on some;
+    a share `interleaved` of them with interleaved lines (axis 1)."""
     r = np.random.default_rng(seed)
     items, off, goff = [], 0, 0
     for i in range(count):
-        n = int(round(10 ** r.uniform(math.log10(7), math.log10(20000))))
-        nl = int(r.choice([1, 1, 2, 3, 5, 17]))
+        n = int(round(10 ** r.uniform(math.log10(7), math.log10(nmax))))
+        nl = int(r.choice(lines))
         bc = "dirichlet" if r.random() < 0.5 else "periodic"
         cells = n if bc == "periodic" else n - 1
         nu = float(10 ** r.uniform(-3, math.log10(20)))
@@ -33,6 +35,8 @@ def small_batch(count=48, seed=7):
         if bc == "dirichlet" and r.random() < 0.5:
             it["g_offset"] = goff
             goff += 2 * nl
+        if interleaved > 0 and r.random() < interleaved:
+            it["axis"] = 1
         items.append(it)
         off += n * nl + int(r.integers(0, 5))  # gaps between instances
     v = np.random.default_rng(seed + 1).standard_normal(off)
@@ -40,24 +44,34 @@ def small_batch(count=48, seed=7):
     return items, v, g
 
 
+def instance_view(it, a):
+    """The instance's points as a 2-D array whose axis `d` holds its lines: (nlines, n) rows of
+    contiguous lines (d = 0), or (n, nlines) with the lines as columns (interleaved, d = 1)."""
+    n, nl, d = it["n"], it["nlines"], it.get("axis", 0)
+    flat = a[it["offset"]:it["offset"] + n * nl]
+    return (flat.reshape(nl, n) if d == 0 else flat.reshape(n, nl)), d
+
+
 def oracle_instance(it, v, g):
     n, nl = it["n"], it["nlines"]
-    x = v[it["offset"]:it["offset"] + n * nl].reshape(nl, n)
-    og = oracle.make_grid((n, nl), (it["lo"], 0.0), (it["hi"], 1.0), (it["bc"], "periodic"))
+    x, d = instance_view(it, v)
+    if d == 0:
+        og = oracle.make_grid((n, nl), (it["lo"], 0.0), (it["hi"], 1.0), (it["bc"], "periodic"))
+    else:
+        og = oracle.make_grid((nl, n), (0.0, it["lo"]), (1.0, it["hi"]), ("periodic", it["bc"]))
     gv = g[it["g_offset"]:it["g_offset"] + 2 * nl].reshape(nl, 2) if it["g_offset"] >= 0 else None
     if it["k"] == 0:
-        ref = oracle.apply_invL(og, 0, it["op"], 6, it["alpha"], x, gv)
+        ref = oracle.apply_invL(og, d, it["op"], 6, it["alpha"], x, gv)
         return ref, np.abs(ref).max()
-    ref = oracle.apply_D_partial_sum(og, 0, it["op"], 6, it["alpha"], 1, it["scale"], x, gv)
+    ref = oracle.apply_D_partial_sum(og, d, it["op"], 6, it["alpha"], 1, it["scale"], x, gv)
     return ref, abs(it["scale"]) * np.abs(x).max()
 
 
 def check_all(items, v, g, got, tol):
     worst = 0.0
     for i, it in enumerate(items):
-        n, nl = it["n"], it["nlines"]
         ref, scale = oracle_instance(it, v, g)
-        out = got[it["offset"]:it["offset"] + n * nl].reshape(nl, n)
+        out = instance_view(it, got)[0]
         e = float(np.abs(out - ref).max() / max(scale, 1e-300))
         worst = max(worst, e)
         assert e < tol, (i, it, e)
@@ -81,6 +95,27 @@ def test_small_batch_all_paths(gpu_lib, dtype, tol):
     check_all(items, v, g, b, tol)
     c = host(plan.apply_per_instance(vd, g=gd))
     check_all(items, v, g, c, tol)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(SC_F64, 1e-12), (SC_F32_MIXED, 1e-5)])
+def test_interleaved_line_instances(gpu_lib, dtype, tol):
+    """Instances whose lines are interleaved (the y lines of small 2-D arrays: 1 to 40 lines of 7 to
+    3000 points, chunked beyond 256 or 512 points) beside contiguous ones: every path, and the
+    tuned plan, against the oracle."""
+    items, v, g = small_batch(count=40, seed=31, interleaved=0.6, nmax=3000, lines=(1, 3, 16, 17, 40))
+    assert sum(it.get("axis", 0) for it in items) >= 15
+    dt = torch.float64 if dtype == SC_F64 else torch.float32
+    plan = BatchPlan(items, dtype=dtype, order=6)
+    vd, gd = to_dev(v, dt), to_dev(g, torch.float64)
+    host = lambda t: (torch.cuda.synchronize(), t.double().cpu().numpy())[1]
+    check_all(items, v, g, host(plan.apply(vd, g=gd)), tol)
+    check_all(items, v, g, host(plan.apply(vd, g=gd, use_graph=True)), tol)
+    check_all(items, v, g, host(plan.apply_per_instance(vd, g=gd)), tol)
+    plan.tune(vd, g=gd, reps=1)
+    shapes = plan.describe()["shapes"]
+    assert {s["axis"] for s in shapes} == {0, 1}
+    check_all(items, v, g, host(plan.apply(vd, g=gd, use_graph=True)), tol)
     plan.close()
 
 
