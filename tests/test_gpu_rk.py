@@ -69,6 +69,22 @@ def test_rk3_mixed_path(gpu_lib):
     assert np.abs(u.double().cpu().numpy() - ref).max() < 1e-5 * np.abs(ref).max()
 
 
+def test_rk3_mixed_path_chunked_lines(gpu_lib):
+    """The mixed path with y lines longer than one tile (1100 points): the stage combinations of
+    those lines run after their partial sums, in FP32 fields; within 1e-5 of the oracle."""
+    import dataclasses
+
+    n = (64, 1100)
+    u0 = W.random_field((n[1], n[0]), index=66)
+    g = Grid(n, (0.0, 0.0), (2 * np.pi, 2 * np.pi * n[1] / n[0]))
+    ref = oracle.time_step_rk(oracle.make_grid(g.n, g.lo, g.hi, g.bc), (1.0, -0.7), 0.05, 0.5, 0.02, 6, 3, u0, 3)
+    u = torch.from_numpy(u0.astype(np.float32)).cuda()
+    sc.time_step(u, dataclasses.replace(g, dtype=SC_F32_MIXED), 3, c=(1.0, -0.7), nu_diff=0.05, beta=0.5, dt=0.02,
+                 order=6, stages=3)
+    torch.cuda.synchronize()
+    assert np.abs(u.double().cpu().numpy() - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 def test_rk_rejects_split_and_dirichlet(gpu_lib):
     u = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
     with pytest.raises(ScError):
