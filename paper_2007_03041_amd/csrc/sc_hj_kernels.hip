@@ -138,6 +138,61 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpOperands &o, const flo
     bar();
 }
 
+// Inference of 16 samples with every product transposed: the weights are the A operand and the
+// samples the B operand, so a layer's result -- lane 16 g + m holding units 4g..4g+3 of sample m --
+// is the next layer's B operand as it stands and the hidden activations stay in registers (the
+// weight registers of mlp_load serve unchanged: A[m][4g..4g+3] of a unit block is what they hold).
+// Each product sums the same terms as mlp_tile_forward's.  The logits of sample m go to
+// z[m][0..2] (LDS) from lanes 0..15.
+struct MlpRowBias {
+    f32x4 b1[2], b2[2], b3;  // biases of units 16 t + 4 g + j (layer 3: unit 4 g + j)
+};
+
+__device__ __forceinline__ MlpRowBias mlp_row_bias(const float *__restrict__ P, int lane)
+{
+    MlpRowBias r;
+    const int g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            r.b1[t][j] = P[MLP_B1 + 16 * t + 4 * g + j];
+            r.b2[t][j] = P[MLP_B2 + 16 * t + 4 * g + j];
+        }
+        r.b3[j] = (4 * g + j) < MLP_OUT ? P[MLP_B3 + 4 * g + j] : 0.f;
+    }
+    return r;
+}
+
+__device__ __forceinline__ void mlp_tile_infer(const MlpOperands &o, const MlpRowBias &rb, const float (*feat)[MLP_IN],
+                                               float (*z)[4], int lane)
+{
+    const int m = lane & 15, g = lane >> 4;
+    bf16x4 x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = (4 * g + j) < MLP_IN ? f2bf(feat[m][4 * g + j]) : (short)0;
+    bf16x4 h1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const f32x4 r = mfma16(o.w1[t], x, rb.b1[t]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h1[t][j] = f2bf(fmaxf(r[j], 0.f));
+    }
+    bf16x4 h2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x4 r = mfma16(o.w2[t][0], h1[0], rb.b2[t]);
+        r = mfma16(o.w2[t][1], h1[1], r);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h2[t][j] = f2bf(fmaxf(r[j], 0.f));
+    }
+    f32x4 r3 = mfma16(o.w3[0], h2[0], rb.b3);
+    r3 = mfma16(o.w3[1], h2[1], r3);
+    if (g == 0)
+#pragma unroll
+        for (int j = 0; j < MLP_OUT; ++j) z[m][j] = r3[j];
+}
+
 __device__ __forceinline__ void softmax3(const float *zz, double *om)
 {
     const double a = zz[0], b = zz[1], c = zz[2];
@@ -203,7 +258,6 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
                                                     const float *__restrict__ P, double *__restrict__ stats)
 {
     __shared__ float feat[512][MLP_IN];
-    __shared__ float hid[4][16][33];
     __shared__ float zo[512][4];
     __shared__ double red[2][4];
     const int tid = threadIdx.x;
@@ -242,8 +296,8 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
         wenoz(sL, A.d, oL);
     }
     if (MODE == HJ_LEARNED) {
-        // Every tile below reads and writes only its own wave's rows of feat, hid and zo (tile T of
-        // wave wv covers its points wv*64 + 16 (T mod 4) ..., stencil R for T < 4, L after), so the
+        // Every tile below reads and writes only its own wave's rows of feat and zo (tile T of wave
+        // wv covers its points wv*64 + 16 (T mod 4) ..., stencil R for T < 4, L after), so the
         // waves synchronise with themselves only: LDS accesses of one wave complete in order, and
         // the fences keep the compiler from moving accesses across the sync points.
         auto bar = [] {
@@ -255,10 +309,12 @@ __global__ void __launch_bounds__(256) hj_weno_quad(const double *__restrict__ u
         stencil_features(sL, feat[256 + tid]);
         bar();
         const MlpOperands o = mlp_load(P, lane);
+        const MlpRowBias rb = mlp_row_bias(P, lane);
         for (int T = 0; T < 8; ++T) {
             const int base = (T >> 2) * 256 + wv * 64 + 16 * (T & 3);
-            mlp_tile_forward(o, &feat[base], hid[wv], &zo[base], (float(*)[16][33]) nullptr, lane, bar);
+            mlp_tile_infer(o, rb, &feat[base], &zo[base], lane);
         }
+        bar();
         double pR[3], pL[3];
         softmax3(zo[tid], pR);
         softmax3(zo[256 + tid], pL);
@@ -687,11 +743,10 @@ __global__ void __launch_bounds__(256) mlp_forward(const float *__restrict__ P, 
                                                    float *__restrict__ Y, int64_t n)
 {
     __shared__ float feat[4][16][MLP_IN];
-    __shared__ float hid[4][16][33];
     __shared__ float zo[4][16][4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const MlpOperands o = mlp_load(P, lane);
-    auto bar = [] { __syncthreads(); };
+    const MlpRowBias rb = mlp_row_bias(P, lane);
     const int64_t ntiles = (n + 15) / 16;
     const int64_t per_block = 4;
     for (int64_t t0 = (int64_t)blockIdx.x * per_block; t0 < ntiles; t0 += (int64_t)gridDim.x * per_block) {
@@ -702,7 +757,8 @@ __global__ void __launch_bounds__(256) mlp_forward(const float *__restrict__ P, 
             feat[wv][e / MLP_IN][e % MLP_IN] = (tile < ntiles && row < n) ? X[row * MLP_IN + e % MLP_IN] : 0.f;
         }
         __syncthreads();
-        mlp_tile_forward(o, feat[wv], hid[wv], zo[wv], (float(*)[16][33]) nullptr, lane, bar);
+        mlp_tile_infer(o, rb, feat[wv], zo[wv], lane);
+        __syncthreads();
         if (lane < 16) {
             const int64_t row = tile * 16 + lane;
             if (tile < ntiles && row < n) {
