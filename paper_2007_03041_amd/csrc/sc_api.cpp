@@ -585,24 +585,24 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order
         OpSpec o{(int)op, alpha, scale, k};
         return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes, st);
     }
-    // chunked lines and k > 1: w_p = D[w_{p-1}] pass by pass, out accumulates scale * w_p
+    // chunked lines and k > 1: the Horner form of the fused passes, S_k = D (I + D (I + ... + D)),
+    // one pass per power: u_1 = v, u_{p+1} = v + D[u_p] (each pass adds v to its result), and the
+    // last pass writes scale D[u_k]
     const size_t need = sc_workspace_bytes(grid, dim, 1, k);
     if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small");
     char *w0 = (char *)ws;
     char *w1 = w0 + round256(bytes);
     char *rest = w1 + round256(bytes);
     const size_t rest_bytes = ws_bytes - 2 * round256(bytes);
-    const void *prev = v;
+    const void *u = v;
     for (int p = 1; p <= k; ++p) {
-        char *dst = (p % 2) ? w0 : w1;
-        OpSpec o{(int)op, alpha, 1.0, 1};
-        s = run_pass(grid, dim, order, &o, 1, prev, nullptr, 0, dst, dirichlet_g, rest, rest_bytes, st);
+        const bool last = p == k;
+        void *dst = last ? out : (void *)((p % 2) ? w0 : w1);
+        OpSpec o{(int)op, alpha, last ? scale : 1.0, 1};
+        s = run_pass(grid, dim, order, &o, 1, u, last ? nullptr : v, last ? 0 : 2, dst, dirichlet_g, rest, rest_bytes,
+                     st);
         if (s != SC_OK) return s;
-        hipError_t e = timed("axpy", st, [&](const char **) {
-            return scx::launch_axpy(ax.total, (int)elem_bytes(grid), scale, dst, out, p == 1 ? 1 : 0, st);
-        });
-        if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
-        prev = dst;
+        u = dst;
     }
     return SC_OK;
 }

@@ -226,13 +226,6 @@ __global__ void __launch_bounds__(256) lincomb_kernel(int64_t nel, double a, con
     if (i < nel) out[i] = (T)fma(a, (double)x[i], b * (double)y[i]);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) axpy_kernel(int64_t nel, double s, const T *x, T *y, int init)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nel) y[i] = init ? (T)(s * (double)x[i]) : (T)fma(s, (double)x[i], (double)y[i]);
-}
-
 // ------------------------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------------------------
@@ -384,16 +377,6 @@ hipError_t launch_sweep(const PassArgs &a, int elem, const void *JL, const void 
     else
         hipLaunchKernelGGL((sweep_kernel<float>), dim3(a.nlines), dim3(256), 0, st, a, (const float *)JL,
                            (const float *)JR, (float *)IL, (float *)IR, ends);
-    return hipGetLastError();
-}
-
-hipError_t launch_axpy(int64_t nel, int elem, double s, const void *x, void *y, int init, hipStream_t st)
-{
-    const dim3 grid((nel + 255) / 256);
-    if (elem == 8)
-        hipLaunchKernelGGL((axpy_kernel<double>), grid, dim3(256), 0, st, nel, s, (const double *)x, (double *)y, init);
-    else
-        hipLaunchKernelGGL((axpy_kernel<float>), grid, dim3(256), 0, st, nel, s, (const float *)x, (float *)y, init);
     return hipGetLastError();
 }
 

@@ -26,7 +26,6 @@ bool pipe_variant(int vid, int elem);
 hipError_t launch_local_quad(const PassArgs &a, int elem, int order, void *JL, void *JR, hipStream_t st);
 hipError_t launch_sweep(const PassArgs &a, int elem, const void *JL, const void *JR, void *IL, void *IR,
                         double *ends, hipStream_t st);
-hipError_t launch_axpy(int64_t nel, int elem, double s, const void *x, void *y, int init, hipStream_t st);
 hipError_t launch_lincomb(int64_t nel, int elem, double a, const void *x, double b, const void *y, void *out,
                           hipStream_t st);
 

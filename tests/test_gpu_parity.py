@@ -158,6 +158,22 @@ STRIDED_CHUNKED = [(4096, "periodic", 4), (4096, "dirichlet", 6), (4608, "dirich
                    (17408, "periodic", 4), (17408, "dirichlet", 6)]
 
 
+@pytest.mark.parametrize("k", [2, 3, 5])
+@pytest.mark.parametrize("n,dim", [(4096, 1), (20000, 0)])
+def test_partial_sums_of_chunked_lines(gpu_lib, k, n, dim):
+    """S_k on periodic lines longer than one tile (y lines of 8 chunks, x lines of 3): one chunked
+    pass per power, every operator, against the oracle's powers."""
+    sc = gpu_lib
+    shape = (n, 5) if dim == 0 else (24, n)
+    v = W.random_field(tuple(reversed(shape)), index=50 + k + dim)
+    g = Grid(shape, (0.0, 0.0), (1.0, 1.0))
+    alpha = 0.4 / g.dx(dim)
+    for op in OPS:
+        ref = oracle.apply_D_partial_sum(ogrid(g), dim, op, 6, alpha, k, -0.7, v)
+        got = host(sc.apply_D_partial_sum(dev(v), g, dim, op, 6, alpha, k, -0.7))
+        assert err(got, ref, max(np.abs(ref).max(), np.abs(v).max())) < TOL, op
+
+
 @pytest.mark.parametrize("n,bc,order", STRIDED_CHUNKED)
 def test_strided_chunked_full_lines(gpu_lib, n, bc, order):
     """y lines that are whole numbers of chunks: 8 chunks (carries formed in the apply launch from
