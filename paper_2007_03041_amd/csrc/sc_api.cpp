@@ -500,10 +500,10 @@ size_t sc_workspace_bytes(const sc_grid *grid, int dim, int which, int k)
     if (which == 2) {
         size_t b = round256((size_t)axis_of(grid, 0).total * elem_bytes(grid));
         if (k >= 2) {
-            // Runge-Kutta stages: stage, Euler result and partial-sum fields, then the partial sums' own
+            // Runge-Kutta stages: two stage fields, then the partial sums' own
             size_t ps = 0;
             for (int d = 0; d < grid->ndim; ++d) ps = std::max(ps, sc_workspace_bytes(grid, d, 1, k));
-            return 3 * b + ps + 256;
+            return 2 * b + ps + 256;
         }
         size_t extra = 0;
         for (int d = 0; d < grid->ndim; ++d) {
@@ -564,6 +564,35 @@ sc_status sc_apply_invL_nn(const sc_grid *grid, int dim, int op, int order, doub
                     (hipStream_t)stream, cpb);
 }
 
+// out = aw acc + scale S_k[v] along `dim` (acc may be out; nullptr: none) for lines longer than one
+// tile: the Horner form of the fused passes, S_k = D (I + D (I + ... + D)), one pass per power --
+// u_1 = v, u_{p+1} = v + D[u_p] (each pass adds v to its result), the last pass writing
+// scale D[u_k] + aw acc.  ws: two fields and the chunk totals (sc_workspace_bytes(grid, dim, 1, k)).
+static sc_status partial_sum_chunked(const sc_grid *grid, int dim, int op, int order, double alpha, int k,
+                                     double scale, const double *dirichlet_g, const void *v, const void *acc,
+                                     double aw, void *out, char *ws, size_t ws_bytes, hipStream_t st)
+{
+    const size_t bytes = (size_t)axis_of(grid, dim).total * elem_bytes(grid);
+    const size_t need = sc_workspace_bytes(grid, dim, 1, k);
+    if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small");
+    char *w0 = ws;
+    char *w1 = w0 + round256(bytes);
+    char *rest = w1 + round256(bytes);
+    const size_t rest_bytes = ws_bytes - 2 * round256(bytes);
+    const void *u = v;
+    for (int p = 1; p <= k; ++p) {
+        const bool last = p == k;
+        void *dst = last ? out : (void *)((p % 2) ? w0 : w1);
+        OpSpec o{op, alpha, last ? scale : 1.0, 1};
+        const sc_status s = last ? run_pass(grid, dim, order, &o, 1, u, acc, acc ? 2 : 0, dst, dirichlet_g, rest,
+                                            rest_bytes, st, 0, 1.0, aw)
+                                 : run_pass(grid, dim, order, &o, 1, u, v, 2, dst, dirichlet_g, rest, rest_bytes, st);
+        if (s != SC_OK) return s;
+        u = dst;
+    }
+    return SC_OK;
+}
+
 sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order, double alpha, int k,
                                  double scale, const double *dirichlet_g, const void *v, void *out, void *ws,
                                  size_t ws_bytes, sc_stream_t stream)
@@ -585,26 +614,8 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order
         OpSpec o{(int)op, alpha, scale, k};
         return run_pass(grid, dim, order, &o, 1, v, nullptr, 0, out, dirichlet_g, (char *)ws, ws_bytes, st);
     }
-    // chunked lines and k > 1: the Horner form of the fused passes, S_k = D (I + D (I + ... + D)),
-    // one pass per power: u_1 = v, u_{p+1} = v + D[u_p] (each pass adds v to its result), and the
-    // last pass writes scale D[u_k]
-    const size_t need = sc_workspace_bytes(grid, dim, 1, k);
-    if (!ws || ws_bytes < need) return fail(SC_ERR_WORKSPACE, "workspace too small");
-    char *w0 = (char *)ws;
-    char *w1 = w0 + round256(bytes);
-    char *rest = w1 + round256(bytes);
-    const size_t rest_bytes = ws_bytes - 2 * round256(bytes);
-    const void *u = v;
-    for (int p = 1; p <= k; ++p) {
-        const bool last = p == k;
-        void *dst = last ? out : (void *)((p % 2) ? w0 : w1);
-        OpSpec o{(int)op, alpha, last ? scale : 1.0, 1};
-        s = run_pass(grid, dim, order, &o, 1, u, last ? nullptr : v, last ? 0 : 2, dst, dirichlet_g, rest, rest_bytes,
-                     st);
-        if (s != SC_OK) return s;
-        u = dst;
-    }
-    return SC_OK;
+    return partial_sum_chunked(grid, dim, op, order, alpha, k, scale, dirichlet_g, v, nullptr, 0.0, out, (char *)ws,
+                               ws_bytes, st);
 }
 
 double sc_effective_dt(const sc_grid *grid, const sc_linear_pde *pde)
@@ -677,12 +688,13 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
         // out = ca acc + cb E(v), E(v) = v + sum over axes and operators of scale S_s[v].  The
         // partial-sum passes form it themselves: the first one adds cb v (and ca acc) to its
         // cb scale S_s[v], each later one adds its own term onto out.  Lines longer than one tile
-        // take their powers of D pass by pass into a scratch field, combined afterwards.
+        // take their powers of D one chunked pass each, the last adding the term onto out (a first
+        // term with ca != 0 starts out as ca acc + cb v).
         const int elem = (int)elem_bytes(grid);
         const int64_t nel = ax0.total;
-        char *U1 = wsp, *B = wsp + round256(fbytes), *TMP = B + round256(fbytes);
-        char *psw = TMP + round256(fbytes);
-        const size_t psw_bytes = ws_bytes - 3 * round256(fbytes);
+        char *U1 = wsp, *B = wsp + round256(fbytes);
+        char *psw = B + round256(fbytes);
+        const size_t psw_bytes = ws_bytes - 2 * round256(fbytes);
         auto lin = [&](double a, const void *x, double b, const void *y, void *o) -> sc_status {
             const hipError_t e = timed("lincomb", st, [&](const char **) {
                 return scx::launch_lincomb(nel, elem, a, x, b, y, o, st);
@@ -702,15 +714,15 @@ sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps
                                              psw_bytes, st, 0, cb, ca)
                                   : run_pass(grid, d, pde->order, &o, 1, v, out, 2, out, nullptr, psw, psw_bytes, st);
                     } else {
-                        r = sc_apply_D_partial_sum(grid, d, op.op, pde->order, op.alpha, stages, cb * op.scale, nullptr,
-                                                   v, TMP, psw, psw_bytes, stream);
-                        if (r == SC_OK) {
-                            if (!first)
-                                r = lin(1.0, out, 1.0, TMP, out);
-                            else if (ca == 0.0)
-                                r = lin(cb, v, 1.0, TMP, out);
-                            else if ((r = lin(cb, v, 1.0, TMP, TMP)) == SC_OK)
-                                r = lin(ca, acc, 1.0, TMP, out);
+                        const double sc = cb * op.scale;
+                        if (first && ca == 0.0) {
+                            r = partial_sum_chunked(grid, d, op.op, pde->order, op.alpha, stages, sc, nullptr, v, v, cb,
+                                                    out, psw, psw_bytes, st);
+                        } else {
+                            r = first ? lin(ca, acc, cb, v, out) : SC_OK;
+                            if (r == SC_OK)
+                                r = partial_sum_chunked(grid, d, op.op, pde->order, op.alpha, stages, sc, nullptr, v,
+                                                        out, 1.0, out, psw, psw_bytes, st);
                         }
                     }
                     if (r != SC_OK) return r;
