@@ -148,8 +148,9 @@ sc_status sc_apply_D_partial_sum(const sc_grid *grid, int dim, int op, int order
  * of grid-scale modes is 1 - d (beta + beta^2) with both operators on d axes, so |.| <= 1 needs
  * d (beta + beta^2) <= 2).  split = 1: dimension splitting -- the same 1-D step applied to each
  * axis in turn, x then y then z, each acting on the previous one's result (per-axis factors of
- * modulus <= 1 at beta = 1).  Dirichlet axes hold u = 0 at both ends.  nn_policy applies the nearest-neighbour time-step bound
- * of Sec. 3.1 with tolerance nn_eps over blocks of length block_len (0 = the whole axis):
+ * modulus <= 1 at beta = 1).  Dirichlet axes hold u = 0 at both ends.  nn_policy applies the
+ * nearest-neighbour time-step bound of Sec. 3.1 with tolerance nn_eps over blocks of length
+ * block_len (0 = the whole axis):
  * 0 = ignore, 1 = reduce dt to the bound, 2 = fail with SC_ERR_ARG if dt exceeds it.
  * stages = s in {2, 3} (Sec. 2.5): an s-stage explicit Runge-Kutta method coupled to partial sums of
  * the same order -- every D above replaced by S_s = sum_{p=1..s} D^p -- in the strong-stability-
@@ -168,7 +169,7 @@ typedef struct {
     double nn_eps;    /* 0 -> 1e-16 */
     double block_len; /* 0 -> axis length */
     int32_t split;    /* 0 additive (unsplit), 1 dimension-split x, y, z */
-    int32_t stages;   /* 0 or 1: the Euler step above; 2, 3: s-stage SSP Runge-Kutta (see below) */
+    int32_t stages;   /* 0 or 1: the Euler step above; 2, 3: s-stage SSP Runge-Kutta (see above) */
 } sc_linear_pde;
 
 sc_status sc_time_step(const sc_grid *grid, const sc_linear_pde *pde, int nsteps, void *u,
