@@ -230,9 +230,10 @@ sc_status sc_batch_apply_per_instance(sc_batch_plan plan, const void *v, void *o
                                       size_t ws_bytes, sc_stream_t stream);
 /* Autotuner: times every candidate tile shape (chunk length and lines per tile of the variants of
  * the class's axis: x-line tiles, or strided tiles of 16 or 32 lines; persistent or one workgroup
- * per work item; windowed or exact chunk carries where the windowed ones apply) on each class of the plan's instances, `reps` runs each, on the caller's
- * arrays (out is overwritten), keeps the fastest per class for this plan and for plans created
- * later in the process (sc_batch_tune_export saves the table).
+ * per work item; windowed or exact chunk carries where the windowed ones apply) on each class of
+ * the plan's instances, `reps` runs each, on the caller's arrays (out is overwritten), keeps the
+ * fastest per class for this plan and for plans created later in the process
+ * (sc_batch_tune_export saves the table).
  * Synchronises `stream`; needs ws_bytes >= sc_batch_workspace_bytes(plan). */
 sc_status sc_batch_tune(sc_batch_plan plan, const void *v, void *out, const double *g, void *ws, size_t ws_bytes,
                         int reps, sc_stream_t stream);
