@@ -46,6 +46,21 @@ def test_rk_3d_matches_oracle(gpu_lib, stages, n):
 
 
 @pytest.mark.parametrize("stages", [2, 3])
+def test_rk_1d_lines_longer_than_a_tile(gpu_lib, stages):
+    """One axis of 20000 points (x lines of three chunks): every stage term goes through the chunked
+    Horner passes, the first one adding onto the stage's combined fields."""
+    n = 20000
+    u0 = W.random_field((n,), index=90 + stages)
+    g = Grid((n,), (0.0,), (2 * np.pi,))
+    c, nu_diff, beta, dt = (1.0,), 0.05, 0.5, 0.02
+    ref = oracle.time_step_rk(oracle.make_grid(g.n, g.lo, g.hi, g.bc), c, nu_diff, beta, dt, 6, 2, u0, stages)
+    u = torch.from_numpy(u0.copy()).cuda()
+    sc.time_step(u, g, 2, c=c, nu_diff=nu_diff, beta=beta, dt=dt, order=6, stages=stages)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("stages", [2, 3])
 def test_rk_without_operators_keeps_the_field(gpu_lib, stages):
     """No advection and no diffusion: every stage is E(v) = v, formed by element-wise combinations
     alone; the field stays what it was (to the rounding of the stage weights)."""
